@@ -8,10 +8,11 @@ never imports the GPU library.  It shares no code with the HIP path.
   float64, OpenMP over targets.
 * ``brute``: an independent NumPy all-pairs implementation for tiny inputs.
 * ``rollout``: the stream-kick-stream subcycle map and its adjoint in float64.
+* ``binning``: the chaining-mesh cell list (keys, stable order, records).
 """
 from .clib import (force, force_vjp, num_threads, build, library_path,
                    rel_err_floored)
-from . import brute, rollout
+from . import brute, rollout, binning
 
 __all__ = ["force", "force_vjp", "num_threads", "build", "library_path",
-           "rel_err_floored", "brute", "rollout"]
+           "rel_err_floored", "brute", "rollout", "binning"]

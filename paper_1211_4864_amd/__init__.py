@@ -1,0 +1,26 @@
+"""Short-range particle-particle gravity of the split-force N-body method
+(Habib et al. 2012, arXiv:1211.4864, Sec. III, Eq. 7) on MI355X (gfx950).
+
+The computation lives in the HIP library ``libhacc_sr.so`` (C ABI declared
+in ``include/hacc_sr.h``); this package only marshals arguments to it.
+"""
+from ._lib import (load, check, strerror, grid_dim, workspace_bytes, bin,
+                   force, force_vjp, kick, stream, kick_adjoint, count_pairs,
+                   timing_enable, timing_read, release_workspace, HaccSrError,
+                   EXPORTS, LIB_PATH, TIMER_FORCE, TIMER_VJP, TIMER_BIN,
+                   TIMER_WORKLIST)
+
+
+def __getattr__(name):
+    # autograd wrappers import torch; load them on first use
+    if name in ("SRForce", "sr_force", "SKSRollout", "rollout_sks", "sks_forward"):
+        from . import autograd
+        return getattr(autograd, name)
+    raise AttributeError(name)
+
+
+__all__ = ["load", "check", "strerror", "grid_dim", "workspace_bytes", "bin",
+           "force", "force_vjp", "kick", "stream", "kick_adjoint",
+           "count_pairs", "timing_enable", "timing_read", "release_workspace",
+           "HaccSrError", "EXPORTS", "LIB_PATH", "SRForce", "sr_force",
+           "SKSRollout", "rollout_sks", "sks_forward"]

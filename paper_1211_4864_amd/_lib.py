@@ -1,0 +1,271 @@
+"""ctypes binding of libhacc_sr.so (declared in include/hacc_sr.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  PyTorch provides device memory (the output tensors and the
+workspace) and the stream (the current torch stream of the tensors'
+device).  The library must be built (``__graft_entry__.build()``); there is
+no fallback, a missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhacc_sr.so")
+
+EXPORTS = (
+    "hacc_sr_version", "hacc_sr_strerror", "hacc_sr_set_stream",
+    "hacc_sr_grid_dim", "hacc_sr_workspace_bytes", "hacc_sr_set_workspace",
+    "hacc_sr_bin", "hacc_sr_force", "hacc_sr_force_vjp", "hacc_sr_kick",
+    "hacc_sr_stream", "hacc_sr_kick_adjoint", "hacc_sr_count_pairs",
+    "hacc_sr_timing_enable", "hacc_sr_timing_read",
+)
+
+OK, EINVAL, EDOMAIN, ENOSPACE, EHIP = 0, -1, -2, -3, -4
+TIMER_FORCE, TIMER_VJP, TIMER_BIN, TIMER_WORKLIST = 0, 1, 2, 3
+
+
+class HaccSrError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"hacc_sr error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load the library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I64, D, F, I = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_double,
+                       ctypes.c_float, ctypes.c_int)
+    sig = {
+        "hacc_sr_version": ([], I),
+        "hacc_sr_strerror": ([I], ctypes.c_char_p),
+        "hacc_sr_set_stream": ([P], I),
+        "hacc_sr_grid_dim": ([D, F, P], I),
+        "hacc_sr_workspace_bytes": ([I64, D, F, P], I),
+        "hacc_sr_set_workspace": ([P, ctypes.c_size_t], I),
+        "hacc_sr_bin": ([P, P, I64, D, F, P, P, P], I),
+        "hacc_sr_force": ([P, P, I64, D, F, F, P, P], I),
+        "hacc_sr_force_vjp": ([P, P, I64, D, F, F, P, P, P], I),
+        "hacc_sr_kick": ([P, P, I64, D], I),
+        "hacc_sr_stream": ([P, P, I64, D, D], I),
+        "hacc_sr_kick_adjoint": ([P, P, I64, D], I),
+        "hacc_sr_count_pairs": ([P, I64, D, F, F, P], I),
+        "hacc_sr_timing_enable": ([I], I),
+        "hacc_sr_timing_read": ([I, P, P], I),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def check(rc: int) -> None:
+    if rc != OK:
+        raise HaccSrError(rc, load().hacc_sr_strerror(rc).decode())
+
+
+def strerror(rc: int) -> str:
+    return load().hacc_sr_strerror(rc).decode()
+
+
+def poly_array(poly: Sequence[float]):
+    """Host float[6] for the polynomial coefficients c_0..c_5."""
+    arr = np.ascontiguousarray(np.asarray(poly, dtype=np.float32).reshape(6))
+    return (ctypes.c_float * 6)(*arr.tolist())
+
+
+def grid_dim(box: float, r_cut: float) -> int:
+    out = ctypes.c_int32(0)
+    check(load().hacc_sr_grid_dim(float(box), float(r_cut), ctypes.byref(out)))
+    return out.value
+
+
+def workspace_bytes(n: int, box: float, r_cut: float) -> int:
+    out = ctypes.c_size_t(0)
+    check(load().hacc_sr_workspace_bytes(int(n), float(box), float(r_cut),
+                                         ctypes.byref(out)))
+    return out.value
+
+
+# ------------------------------------------------------------------ torch side
+
+def _torch():
+    import torch
+    return torch
+
+
+_workspaces: dict = {}
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _require(t, dtype, shape, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _bind(device, n: int, box: float, r_cut: float) -> None:
+    """Register torch's current stream and a workspace large enough for n."""
+    torch = _torch()
+    lib = load()
+    dev = torch.device(device)
+    stream = torch.cuda.current_stream(dev)
+    check(lib.hacc_sr_set_stream(ctypes.c_void_p(stream.cuda_stream)))
+    need = workspace_bytes(n, box, r_cut)
+    key = dev.index if dev.index is not None else torch.cuda.current_device()
+    ws = _workspaces.get(key)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(int(need * 1.125) + 4096, dtype=torch.uint8, device=dev)
+        _workspaces[key] = ws
+    check(lib.hacc_sr_set_workspace(_ptr(ws), ws.numel()))
+
+
+def release_workspace() -> None:
+    _workspaces.clear()
+    if _lib is not None:
+        _lib.hacc_sr_set_workspace(None, 0)
+
+
+def bin(pos, mass, box: float, r_cut: float):
+    """Chaining-mesh binning: returns (cell_start int32 (N^3+1),
+    perm int32 (n), sorted_rec float32 (n, 4))."""
+    torch = _torch()
+    n = pos.shape[0]
+    _require(pos, torch.float64, (n, 3), "pos")
+    _require(mass, torch.float32, (n,), "mass")
+    N = grid_dim(box, r_cut)
+    cs = torch.empty(N ** 3 + 1, dtype=torch.int32, device=pos.device)
+    perm = torch.empty(n, dtype=torch.int32, device=pos.device)
+    rec = torch.empty((n, 4), dtype=torch.float32, device=pos.device)
+    with torch.cuda.device(pos.device):
+        _bind(pos.device, n, box, r_cut)
+        check(load().hacc_sr_bin(_ptr(pos), _ptr(mass), n, float(box),
+                                 float(r_cut), _ptr(cs), _ptr(perm), _ptr(rec)))
+    return cs, perm, rec
+
+
+def force(pos, mass, box: float, r_cut: float, eps: float, poly, out=None):
+    """Short-range accelerations (n, 3) float32 in input order."""
+    torch = _torch()
+    n = pos.shape[0]
+    _require(pos, torch.float64, (n, 3), "pos")
+    _require(mass, torch.float32, (n,), "mass")
+    if out is None:
+        out = torch.empty((n, 3), dtype=torch.float32, device=pos.device)
+    _require(out, torch.float32, (n, 3), "out")
+    with torch.cuda.device(pos.device):
+        _bind(pos.device, n, box, r_cut)
+        check(load().hacc_sr_force(_ptr(pos), _ptr(mass), n, float(box),
+                                   float(r_cut), float(eps), poly_array(poly),
+                                   _ptr(out)))
+    return out
+
+
+def force_vjp(pos, mass, box: float, r_cut: float, eps: float, poly, grad_acc,
+              out=None):
+    """dL/dx (n, 3) float64 for L = sum(grad_acc * acc)."""
+    torch = _torch()
+    n = pos.shape[0]
+    _require(pos, torch.float64, (n, 3), "pos")
+    _require(mass, torch.float32, (n,), "mass")
+    _require(grad_acc, torch.float32, (n, 3), "grad_acc")
+    if out is None:
+        out = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+    _require(out, torch.float64, (n, 3), "out")
+    with torch.cuda.device(pos.device):
+        _bind(pos.device, n, box, r_cut)
+        check(load().hacc_sr_force_vjp(_ptr(pos), _ptr(mass), n, float(box),
+                                       float(r_cut), float(eps),
+                                       poly_array(poly), _ptr(grad_acc),
+                                       _ptr(out)))
+    return out
+
+
+def kick(vel, acc, dt: float) -> None:
+    """vel += dt * acc in place (float64 += float32)."""
+    torch = _torch()
+    n = vel.shape[0]
+    _require(vel, torch.float64, (n, 3), "vel")
+    _require(acc, torch.float32, (n, 3), "acc")
+    with torch.cuda.device(vel.device):
+        check(load().hacc_sr_set_stream(
+            ctypes.c_void_p(torch.cuda.current_stream(vel.device).cuda_stream)))
+        check(load().hacc_sr_kick(_ptr(vel), _ptr(acc), n, float(dt)))
+
+
+def stream(pos, vel, dt: float, box: float) -> None:
+    """pos += dt * vel in place, wrapped into [0, box) when box > 0."""
+    torch = _torch()
+    n = pos.shape[0]
+    _require(pos, torch.float64, (n, 3), "pos")
+    _require(vel, torch.float64, (n, 3), "vel")
+    with torch.cuda.device(pos.device):
+        check(load().hacc_sr_set_stream(
+            ctypes.c_void_p(torch.cuda.current_stream(pos.device).cuda_stream)))
+        check(load().hacc_sr_stream(_ptr(pos), _ptr(vel), n, float(dt), float(box)))
+
+
+def kick_adjoint(grad_vel, dt: float, out=None):
+    """float32(dt * grad_vel)."""
+    torch = _torch()
+    n = grad_vel.shape[0]
+    _require(grad_vel, torch.float64, (n, 3), "grad_vel")
+    if out is None:
+        out = torch.empty((n, 3), dtype=torch.float32, device=grad_vel.device)
+    _require(out, torch.float32, (n, 3), "out")
+    with torch.cuda.device(grad_vel.device):
+        check(load().hacc_sr_set_stream(
+            ctypes.c_void_p(torch.cuda.current_stream(grad_vel.device).cuda_stream)))
+        check(load().hacc_sr_kick_adjoint(_ptr(grad_vel), _ptr(out), n, float(dt)))
+    return out
+
+
+def count_pairs(pos, box: float, r_cut: float, eps: float):
+    """(candidate pairs, pairs inside r_cut) the pair kernel evaluates."""
+    torch = _torch()
+    n = pos.shape[0]
+    _require(pos, torch.float64, (n, 3), "pos")
+    out = torch.zeros(2, dtype=torch.int64, device=pos.device)
+    with torch.cuda.device(pos.device):
+        _bind(pos.device, n, box, r_cut)
+        check(load().hacc_sr_count_pairs(_ptr(pos), n, float(box), float(r_cut),
+                                         float(eps), _ptr(out)))
+    c = out.cpu().tolist()
+    return int(c[0]), int(c[1])
+
+
+def timing_enable(on: bool = True) -> None:
+    check(load().hacc_sr_timing_enable(1 if on else 0))
+
+
+def timing_read(which: int):
+    """(launches, total milliseconds) recorded for a timer since enabling."""
+    n = ctypes.c_int64(0)
+    ms = ctypes.c_double(0.0)
+    check(load().hacc_sr_timing_read(int(which), ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value

@@ -1,0 +1,346 @@
+// Chaining-mesh binning: cell keys and occupancy histogram, exclusive prefix
+// scan, stable LSD radix scatter (so particles keep their input order inside
+// a cell), and the gather of cell-relative float32 records.
+//
+// The chaining mesh is the cell list of the particle-particle part of a
+// P^3M code (Habib et al. 2012, Sec. II); cells are at least r_cut wide so
+// that all short-range partners of a particle lie in the 27 adjacent cells.
+#include "common.h"
+
+namespace hsr {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kItems = 16;
+constexpr int kTile = kBlock * kItems;   // 4096 elements per block
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    const int l = lane_id();
+    return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// Lanes of the wave holding the same 8-bit value (a match over 8 ballots).
+__device__ __forceinline__ uint64_t peers8(unsigned v, bool active) {
+    uint64_t m = __ballot(active);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const bool bit = (v >> b) & 1u;
+        const uint64_t bl = __ballot(bit && active);
+        m &= bit ? bl : ~bl;
+    }
+    return active ? m : 0ull;
+}
+
+// Wrapped (periodic) or raw (open) coordinate and its cell index on one
+// axis.  x == box after the wrap maps to 0; a non-finite coordinate lands in
+// cell 0 (its record then carries the NaN and so do its accelerations).
+__device__ __forceinline__ int axis_cell(double x, const Geom& g, double* xw) {
+    double v = x;
+    if (g.periodic) {
+        v = x - g.box * floor(x / g.box);
+        if (v >= g.box) v -= g.box;
+    }
+    const double k = floor(v / g.Lc);
+    int c;
+    if (!(k >= 0.0)) c = 0;
+    else if (!(k <= (double)(g.N - 1))) c = g.N - 1;
+    else c = (int)k;
+    *xw = v;
+    return c;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cell_keys(
+    const double* __restrict__ pos, int n, Geom g, int* __restrict__ keys,
+    int* __restrict__ vals, int* __restrict__ counts) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const bool active = i < n;
+    int key = 0;
+    if (active) {
+        double xw;
+        const int cx = axis_cell(pos[3 * (int64_t)i], g, &xw);
+        const int cy = axis_cell(pos[3 * (int64_t)i + 1], g, &xw);
+        const int cz = axis_cell(pos[3 * (int64_t)i + 2], g, &xw);
+        key = (cx * g.N + cy) * g.N + cz;
+        keys[i] = key;
+        vals[i] = i;
+    }
+    // Histogram with the first lane's cell aggregated over the wave: inputs
+    // that arrive spatially ordered then cost one atomic per run.
+    const int lead = __shfl(key, __ffsll((unsigned long long)__ballot(active)) - 1);
+    const uint64_t same = __ballot(active && key == lead);
+    if (active) {
+        if (key == lead) {
+            if ((uint64_t)(same & lanemask_lt()) == 0ull)
+                atomicAdd(&counts[key], __popcll(same));
+        } else {
+            atomicAdd(&counts[key], 1);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- scan
+// Exclusive prefix sum of int32 in three passes: per-block sums, a single
+// block scan of those sums, per-block scan plus carry.
+
+__device__ __forceinline__ int wave_incl_scan(int v) {
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int o = __shfl_up(v, d);
+        if (lane_id() >= d) v += o;
+    }
+    return v;
+}
+
+// Block-wide exclusive scan of one value per thread; returns the prefix and
+// writes the block total.
+__device__ __forceinline__ int block_excl_scan(int v, int* total) {
+    __shared__ int wsum[kBlock / kWave];
+    const int incl = wave_incl_scan(v);
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == kWave - 1) wsum[w] = incl;
+    __syncthreads();
+    int base = 0, tot = 0;
+#pragma unroll
+    for (int q = 0; q < kBlock / kWave; ++q) {
+        const int s = wsum[q];
+        if (q < w) base += s;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return base + incl - v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(
+    const int* __restrict__ in, int n, int* __restrict__ bsum) {
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    int s = 0;
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+        const int64_t e = base + it * kBlock + threadIdx.x;
+        if (e < n) s += in[e];
+    }
+    int tot;
+    block_excl_scan(s, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+// One block scans an array of any length in chunks, carrying the total.
+__global__ __launch_bounds__(kBlock) void k_scan_single(int* __restrict__ a,
+                                                        int n) {
+    int carry = 0;
+    for (int64_t c0 = 0; c0 < n; c0 += kTile) {
+        int v[kItems];
+        int s = 0;
+        const int64_t b = c0 + (int64_t)threadIdx.x * kItems;
+#pragma unroll
+        for (int q = 0; q < kItems; ++q) {
+            v[q] = (b + q < n) ? a[b + q] : 0;
+            s += v[q];
+        }
+        int tot;
+        int pre = block_excl_scan(s, &tot) + carry;
+#pragma unroll
+        for (int q = 0; q < kItems; ++q) {
+            if (b + q < n) a[b + q] = pre;
+            pre += v[q];
+        }
+        carry += tot;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_apply(
+    const int* in, int* out, int n, const int* __restrict__ bsum) {
+    const int64_t b = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
+    int v[kItems];
+    int s = 0;
+#pragma unroll
+    for (int q = 0; q < kItems; ++q) {
+        v[q] = (b + q < n) ? in[b + q] : 0;
+        s += v[q];
+    }
+    int tot;
+    int pre = block_excl_scan(s, &tot) + bsum[blockIdx.x];
+#pragma unroll
+    for (int q = 0; q < kItems; ++q) {
+        if (b + q < n) out[b + q] = pre;
+        pre += v[q];
+    }
+}
+
+// ---------------------------------------------------------------- radix
+// One stable counting-sort pass on an 8-bit digit of the cell key.
+
+__global__ __launch_bounds__(kBlock) void k_radix_hist(
+    const int* __restrict__ keys, int n, int shift, int* __restrict__ hist,
+    int nblocks) {
+    __shared__ int h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+#pragma unroll 4
+    for (int it = 0; it < kItems; ++it) {
+        const int64_t e = base + it * kBlock + threadIdx.x;
+        const bool active = e < n;
+        const unsigned d = active ? ((unsigned)keys[e] >> shift) & 255u : 0u;
+        const uint64_t pm = peers8(d, active);
+        if (active && (pm & lanemask_lt()) == 0ull) atomicAdd(&h[d], __popcll(pm));
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kBlock) void k_radix_scatter(
+    const int* __restrict__ kin, const int* __restrict__ vin,
+    int* __restrict__ kout, int* __restrict__ vout, int n, int shift,
+    const int* __restrict__ offs, int nblocks) {
+    constexpr int kW = kBlock / kWave;
+    __shared__ int base_d[256];     // global offset of this block's digit d
+    __shared__ int run_d[256];      // digit d entries already placed by this block
+    __shared__ int wcnt[kW][256];
+    base_d[threadIdx.x] = offs[(int64_t)threadIdx.x * nblocks + blockIdx.x];
+    run_d[threadIdx.x] = 0;
+    const int w = threadIdx.x / kWave;
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    for (int it = 0; it < kItems; ++it) {
+#pragma unroll
+        for (int q = 0; q < kW; ++q) wcnt[q][threadIdx.x] = 0;
+        __syncthreads();
+        const int64_t e = base + it * kBlock + threadIdx.x;
+        const bool active = e < n;
+        const int key = active ? kin[e] : 0;
+        const int val = active ? vin[e] : 0;
+        const unsigned d = ((unsigned)key >> shift) & 255u;
+        const uint64_t pm = peers8(d, active);
+        const int rank = __popcll(pm & lanemask_lt());
+        if (active && rank == 0) wcnt[w][d] = __popcll(pm);
+        __syncthreads();
+        // digit t: exclusive prefix over the waves of this round
+        {
+            const int t = threadIdx.x;
+            int acc = run_d[t];
+#pragma unroll
+            for (int q = 0; q < kW; ++q) {
+                const int c = wcnt[q][t];
+                wcnt[q][t] = acc;
+                acc += c;
+            }
+            run_d[t] = acc;
+        }
+        __syncthreads();
+        if (active) {
+            const int dst = base_d[d] + wcnt[w][d] + rank;
+            kout[dst] = key;
+            vout[dst] = val;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_gather_records(
+    const double* __restrict__ pos, const float* __restrict__ mass,
+    const int* __restrict__ keys, const int* __restrict__ perm, int n, Geom g,
+    float4* __restrict__ rec) {
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n) return;
+    const int i = perm[k];
+    const int key = keys[k];
+    const int cz = key % g.N;
+    const int cy = (key / g.N) % g.N;
+    const int cx = key / (g.N * g.N);
+    double xw, yw, zw;
+    axis_cell(pos[3 * (int64_t)i], g, &xw);
+    axis_cell(pos[3 * (int64_t)i + 1], g, &yw);
+    axis_cell(pos[3 * (int64_t)i + 2], g, &zw);
+    float4 r;
+    r.x = (float)(xw - (double)cx * g.Lc);
+    r.y = (float)(yw - (double)cy * g.Lc);
+    r.z = (float)(zw - (double)cz * g.Lc);
+    r.w = mass ? mass[i] : 0.0f;
+    rec[k] = r;
+}
+
+__global__ __launch_bounds__(kBlock) void k_gather_vec3(
+    const float* __restrict__ v, const int* __restrict__ perm, int n,
+    float4* __restrict__ out) {
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n) return;
+    const int64_t i = perm[k];
+    out[k] = make_float4(v[3 * i], v[3 * i + 1], v[3 * i + 2], 0.0f);
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_i32(int* p, int n, int value) {
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k < n) p[k] = value;
+}
+
+inline int blocks_for(int64_t n, int per) { return (int)((n + per - 1) / per); }
+
+}  // namespace
+
+hipError_t launch_cell_keys(const double* pos, int n, Geom g, int* keys,
+                            int* vals, int* counts, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cell_keys, dim3(blocks_for(n, kBlock)), dim3(kBlock),
+                       0, st, pos, n, g, keys, vals, counts);
+    return hipGetLastError();
+}
+
+size_t scan_tmp_ints(int n) { return (size_t)blocks_for(n, kTile) + 1; }
+
+hipError_t launch_scan_exclusive(const int* in, int* out, int n, int* tmp,
+                                 hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int nb = blocks_for(n, kTile);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, st, in, n, tmp);
+    hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kBlock), 0, st, tmp, nb);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kBlock), 0, st, in, out, n,
+                       (const int*)tmp);
+    return hipGetLastError();
+}
+
+int radix_blocks(int n) { return blocks_for(n, kTile); }
+
+hipError_t launch_radix_pass(const int* kin, const int* vin, int* kout,
+                             int* vout, int n, int shift, int* hist,
+                             int* scan_tmp, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int nb = radix_blocks(n);
+    hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kBlock), 0, st, kin, n,
+                       shift, hist, nb);
+    hipError_t e = launch_scan_exclusive(hist, hist, 256 * nb, scan_tmp, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kBlock), 0, st, kin,
+                       vin, kout, vout, n, shift, (const int*)hist, nb);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_records(const double* pos, const float* mass,
+                                 const int* keys_sorted, const int* perm,
+                                 int n, Geom g, float4* rec, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_records, dim3(blocks_for(n, kBlock)),
+                       dim3(kBlock), 0, st, pos, mass, keys_sorted, perm, n, g,
+                       rec);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_vec3(const float* v, const int* perm, int n,
+                              float4* out, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_vec3, dim3(blocks_for(n, kBlock)), dim3(kBlock),
+                       0, st, v, perm, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int* p, int n, int value, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0,
+                       st, p, n, value);
+    return hipGetLastError();
+}
+
+}  // namespace hsr

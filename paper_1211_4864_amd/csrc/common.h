@@ -1,0 +1,103 @@
+// Internal definitions shared by the HIP translation units of libhacc_sr.
+// Not part of the public interface (include/hacc_sr.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hsr {
+
+constexpr int kWave = 64;
+
+// Chaining-mesh geometry: N^3 cells of side Lc = |box| / N >= r_cut.
+struct Geom {
+    int N;            // cells per axis
+    int periodic;     // 1: periodic cube [0, box); 0: open domain [0, box)
+    double box;       // |box|
+    double Lc;        // cell side, float64
+    float Lc_f;       // cell side rounded to float32 (frame shifts)
+};
+
+// Pair-kernel constants derived on the host from (r_cut, eps, poly).
+// The grid-force polynomial is evaluated in t = alpha * (s + eps) + beta,
+// which maps s in [0, r_cut^2] onto [-1, 1]; b[] are its coefficients in t
+// and db2[] those of 2 d(poly)/ds, also in t.
+struct PairParams {
+    float alpha, beta;
+    float eps;
+    float rc2e;       // float32(r_cut^2 + eps): cut-off test on s + eps
+    float b[6];
+    float db2[5];
+};
+
+// One unit of pair-kernel work: up to kItemI target particles drawn from a
+// run of nz consecutive cells of one (x, y) column, starting at cell key0.
+struct WorkItem {
+    int i_begin;      // first sorted entry of the targets
+    int i_count;      // number of targets (1..kItemI)
+    int key0;         // cell index of the run's first cell
+    int nz;           // cells in the run (1..kMaxRun)
+};
+
+constexpr int kItemI = 64;     // targets per item: one per lane of a wave
+// Runs are capped at two cells: frame coordinates then stay within two cell
+// sides of the origin (the run's centre), which keeps float32 separations of
+// close pairs as precise as in single-cell frames.
+constexpr int kMaxRun = 2;
+
+// ---- launch wrappers (each defined in the translation unit of its kernels)
+
+// binning (bin.hip)
+hipError_t launch_cell_keys(const double* pos, int n, Geom g, int* keys,
+                            int* vals, int* counts, hipStream_t st);
+size_t scan_tmp_ints(int n);
+hipError_t launch_scan_exclusive(const int* in, int* out, int n, int* tmp,
+                                 hipStream_t st);
+int radix_blocks(int n);
+hipError_t launch_radix_pass(const int* kin, const int* vin, int* kout,
+                             int* vout, int n, int shift, int* hist,
+                             int* scan_tmp, hipStream_t st);
+hipError_t launch_gather_records(const double* pos, const float* mass,
+                                 const int* keys_sorted, const int* perm,
+                                 int n, Geom g, float4* rec, hipStream_t st);
+hipError_t launch_gather_vec3(const float* v, const int* perm, int n,
+                              float4* out, hipStream_t st);
+hipError_t launch_fill_i32(int* p, int n, int value, hipStream_t st);
+
+// work list (worklist.hip)
+constexpr int kCostBuckets = 128;
+hipError_t launch_items_count(const int* cell_start, Geom g, int zmax,
+                              int* col_items, hipStream_t st);
+hipError_t launch_items_write(const int* cell_start, Geom g, int zmax,
+                              const int* col_off, WorkItem* items,
+                              hipStream_t st);
+hipError_t launch_items_order(const WorkItem* items, const int* n_items_dev,
+                              int max_items, const int* cell_start, Geom g,
+                              int* bucket_of, int* bucket_count,
+                              int* bucket_off, WorkItem* items_sorted,
+                              int* scan_tmp, hipStream_t st);
+
+// pair kernels (pair.hip)
+hipError_t launch_pair_force(const WorkItem* items, int max_items,
+                             const int* n_items_dev, const float4* rec,
+                             const int* cell_start, const int* perm, Geom g,
+                             PairParams p, float* out_acc, hipStream_t st);
+hipError_t launch_pair_count(const WorkItem* items, int max_items,
+                             const int* n_items_dev, const float4* rec,
+                             const int* cell_start, Geom g, PairParams p,
+                             unsigned long long* counts, hipStream_t st);
+hipError_t launch_pair_vjp(const WorkItem* items, int max_items,
+                           const int* n_items_dev, const float4* rec,
+                           const float4* gsorted, const int* cell_start,
+                           const int* perm, Geom g, PairParams p,
+                           double* out_grad, hipStream_t st);
+
+// kick / stream (integrate.hip)
+hipError_t launch_kick(double* vel, const float* acc, int64_t m, double dt,
+                       hipStream_t st);
+hipError_t launch_stream(double* pos, const double* vel, int64_t m, double dt,
+                         double box, hipStream_t st);
+hipError_t launch_kick_adjoint(const double* gv, float* ga, int64_t m,
+                               double dt, hipStream_t st);
+
+}  // namespace hsr

@@ -1,0 +1,424 @@
+// Pair kernels of the short-range force (Habib et al. 2012, Sec. III,
+// Eq. 7):  a_i = sum_j m_j f(s) d,  f(s) = (s + eps)^(-3/2) - poly5(s),
+// zero for s >= r_cut^2, and its vector-Jacobian product.
+//
+// Layout of the work: one wave (64 lanes) per work item.  Each lane owns one
+// target particle in registers; the item's sources (the 27-cell stencil of
+// its cells, read as 9 z-runs of consecutive sorted entries) are staged
+// through LDS in tiles, already shifted into the item's frame (the lower
+// x, y corner of its column and the lower z face of the run's centre cell),
+// and every lane reads each staged source as an LDS broadcast.  This is the GPU analogue of the paper's contiguous,
+// pre-shifted neighbour lists shared by all particles of a leaf (Sec. III,
+// paragraph after Eq. 7): equal-length lists, balanced lanes, no gathers in
+// the inner loop.
+//
+// Arithmetic: pair terms in float32 on cell-relative coordinates (every
+// coordinate in a frame is within a few cells of the origin, so differences
+// keep their bits); the cut-off is a select, not a branch (the paper's fsel,
+// Sec. III); partial sums over 32 sources are merged into a Kahan-compensated
+// float32 accumulator.  The grid-force polynomial is evaluated by Horner in
+// t = alpha (s + eps) + beta, in [-1, 1] over the cut-off range, whose
+// coefficients the host derives in float64 from the caller's s-basis ones.
+// The library is compiled without floating-point contraction; every fused
+// multiply-add below is written explicitly.
+#include "common.h"
+
+namespace hsr {
+
+namespace {
+
+constexpr int kT = 256;      // sources per LDS tile
+constexpr int kSub = 32;     // sources between compensated merges
+constexpr int kUnroll = 8;   // tile counts are padded to a multiple of this
+constexpr int kSeg = 64;     // segment table entries (one per lane)
+
+static_assert(9 * (kMaxRun + 2) <= kSeg, "segment table too small");
+static_assert(kItemI == kWave, "one target per lane");
+
+__device__ __forceinline__ int wave_incl_scan(int v) {
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int o = __shfl_up(v, d);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+__device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
+    const float y = x - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+// Coordinate shifted by `cells` cell sides into the item frame.  Targets and
+// sources use this same expression, so a particle meets itself at d = 0.
+__device__ __forceinline__ float frame(float rel, int cells, float Lc) {
+    return __builtin_fmaf((float)cells, Lc, rel);
+}
+
+struct Segments {
+    int off[kSeg + 1];   // first tile position of each segment; off[kSeg] = total
+    int start[kSeg];     // first sorted entry of the segment's cell
+    int code[kSeg];      // (dx+1) | (dy+1) << 4 | zi << 8; zi = window cell 0..nz+1
+};
+
+// Cell of the run that serves as the frame origin along z (its centre).
+__device__ __forceinline__ int frame_cell(const WorkItem& it) { return it.nz / 2; }
+
+// Builds the segment table of one item (one cell of the stencil per lane)
+// and returns the number of sources.  Must be called by the whole wave.
+__device__ int build_segments(const WorkItem& it, const int* __restrict__ cs,
+                              const Geom& g, Segments& sg) {
+    const int lane = threadIdx.x;
+    const int N = g.N;
+    const int z0 = it.key0 % N;
+    const int col = it.key0 / N;
+    const int cx = col / N, cy = col % N;
+    const int L = it.nz + 2;
+    int cnt = 0, start = 0, code = 0;
+    if (lane < 9 * L) {
+        const int ca = lane / L, zi = lane - ca * L;
+        const int a = ca / 3 - 1, b = ca % 3 - 1;
+        int x = cx + a, y = cy + b, z = z0 - 1 + zi;
+        bool ok = true;
+        if (g.periodic) {
+            x = x < 0 ? x + N : (x >= N ? x - N : x);
+            y = y < 0 ? y + N : (y >= N ? y - N : y);
+            z = z < 0 ? z + N : (z >= N ? z - N : z);
+        } else {
+            ok = x >= 0 && x < N && y >= 0 && y < N && z >= 0 && z < N;
+        }
+        if (ok) {
+            const int key = (x * N + y) * N + z;
+            start = cs[key];
+            cnt = cs[key + 1] - start;
+        }
+        code = (a + 1) | ((b + 1) << 4) | (zi << 8);
+    }
+    const int incl = wave_incl_scan(cnt);
+    const int total = __shfl(incl, kWave - 1);
+    sg.off[lane] = incl - cnt;
+    sg.start[lane] = start;
+    sg.code[lane] = code;
+    if (lane == 0) sg.off[kSeg] = total;
+    return total;
+}
+
+// Segment holding tile position p (0 <= p < total): the last entry whose
+// offset is <= p.  Empty segments share offsets with the next one.
+__device__ __forceinline__ int find_segment(const Segments& sg, int p) {
+    int lo = 0;
+#pragma unroll
+    for (int step = kSeg / 2; step >= 1; step >>= 1)
+        if (sg.off[lo + step] <= p) lo += step;
+    return lo;
+}
+
+// Source record at tile position p, shifted into the frame.  Window cell zi
+// lies zi - 1 - zc cells above the frame origin.
+__device__ __forceinline__ float4 staged_source(const Segments& sg, int p,
+                                                const float4* __restrict__ rec,
+                                                float Lc, int zc,
+                                                int* sorted_index) {
+    const int s = find_segment(sg, p);
+    const int k = sg.start[s] + (p - sg.off[s]);
+    const int code = sg.code[s];
+    const float4 r = rec[k];
+    *sorted_index = k;
+    return make_float4(frame(r.x, (code & 15) - 1, Lc),
+                       frame(r.y, ((code >> 4) & 15) - 1, Lc),
+                       frame(r.z, (code >> 8) - 1 - zc, Lc), r.w);
+}
+
+// Target of this lane in the frame: its cell inside the run fixes dz.
+__device__ __forceinline__ float4 load_target(const WorkItem& it,
+                                              const int* __restrict__ cs,
+                                              const float4* __restrict__ rec,
+                                              float Lc, int* k_out) {
+    const int lane = threadIdx.x;
+    float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
+    int k = -1;
+    if (lane < it.i_count) {
+        k = it.i_begin + lane;
+        const float4 r = rec[k];
+        int dz = 0;
+        for (int q = 1; q < it.nz; ++q)
+            if (k >= cs[it.key0 + q]) dz = q;
+        t = make_float4(r.x, r.y, frame(r.z, dz - frame_cell(it), Lc), r.w);
+    }
+    *k_out = k;
+    return t;
+}
+
+// Padding source: zero mass, so it adds exactly zero whether or not it falls
+// inside the cut-off (the select discards any non-finite f beyond it).
+__device__ __forceinline__ float4 pad_source(float Lc) {
+    return make_float4(-4.0f * Lc, -4.0f * Lc, -4.0f * Lc, 0.0f);
+}
+
+// ------------------------------------------------------------ forward
+
+__global__ __launch_bounds__(kWave) void k_pair_force(
+    const WorkItem* __restrict__ items, const int* __restrict__ n_items_dev,
+    const float4* __restrict__ rec, const int* __restrict__ cs,
+    const int* __restrict__ perm, Geom g, PairParams P,
+    float* __restrict__ out_acc) {
+    __shared__ Segments sg;
+    __shared__ float4 tile[kT];
+    if ((int)blockIdx.x >= *n_items_dev) return;
+    const WorkItem it = items[blockIdx.x];
+    const int lane = threadIdx.x;
+    const float Lc = g.Lc_f;
+    const int total = build_segments(it, cs, g, sg);
+    const int zc = frame_cell(it);
+    int ki;
+    const float4 xi = load_target(it, cs, rec, Lc, &ki);
+    __syncthreads();
+
+    const float eps = P.eps, rc2e = P.rc2e, alpha = P.alpha, beta = P.beta;
+    const float b0 = P.b[0], b1 = P.b[1], b2 = P.b[2], b3 = P.b[3], b4 = P.b[4],
+                b5 = P.b[5];
+    float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
+
+    for (int t0 = 0; t0 < total; t0 += kT) {
+        const int cnt = min(kT, total - t0);
+        const int cntp = (cnt + kUnroll - 1) & ~(kUnroll - 1);
+        for (int q = lane; q < cntp; q += kWave) {
+            int kk;
+            tile[q] = q < cnt ? staged_source(sg, t0 + q, rec, Lc, zc, &kk) : pad_source(Lc);
+        }
+        __syncthreads();
+        for (int j0 = 0; j0 < cntp; j0 += kSub) {
+            float tx = 0.f, ty = 0.f, tz = 0.f;
+            const int lim = min(j0 + kSub, cntp);
+            for (int jj = j0; jj < lim; jj += kUnroll) {
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    const float4 pj = tile[jj + u];
+                    const float dx = pj.x - xi.x;
+                    const float dy = pj.y - xi.y;
+                    const float dz = pj.z - xi.z;
+                    float sp = __builtin_fmaf(dx, dx, eps);
+                    sp = __builtin_fmaf(dy, dy, sp);
+                    sp = __builtin_fmaf(dz, dz, sp);
+                    const float y = __builtin_amdgcn_rsqf(sp);
+                    const float t = __builtin_fmaf(sp, alpha, beta);
+                    float p = __builtin_fmaf(b5, t, b4);
+                    p = __builtin_fmaf(p, t, b3);
+                    p = __builtin_fmaf(p, t, b2);
+                    p = __builtin_fmaf(p, t, b1);
+                    p = __builtin_fmaf(p, t, b0);
+                    const float y2 = y * y;
+                    const float f = __builtin_fmaf(y2, y, -p);
+                    const float mf = sp < rc2e ? pj.w * f : 0.0f;
+                    tx = __builtin_fmaf(mf, dx, tx);
+                    ty = __builtin_fmaf(mf, dy, ty);
+                    tz = __builtin_fmaf(mf, dz, tz);
+                }
+            }
+            kahan_add(sx, cx, tx);
+            kahan_add(sy, cy, ty);
+            kahan_add(sz, cz, tz);
+        }
+        __syncthreads();
+    }
+    if (ki >= 0) {
+        const int64_t o = 3 * (int64_t)perm[ki];
+        out_acc[o] = sx - cx;
+        out_acc[o + 1] = sy - cy;
+        out_acc[o + 2] = sz - cz;
+    }
+}
+
+// ------------------------------------------------------------ pair counts
+
+__global__ __launch_bounds__(kWave) void k_pair_count(
+    const WorkItem* __restrict__ items, const int* __restrict__ n_items_dev,
+    const float4* __restrict__ rec, const int* __restrict__ cs, Geom g,
+    PairParams P, unsigned long long* __restrict__ counts) {
+    __shared__ Segments sg;
+    __shared__ float4 tile[kT];
+    __shared__ int tidx[kT];
+    if ((int)blockIdx.x >= *n_items_dev) return;
+    const WorkItem it = items[blockIdx.x];
+    const int lane = threadIdx.x;
+    const float Lc = g.Lc_f;
+    const int total = build_segments(it, cs, g, sg);
+    const int zc = frame_cell(it);
+    int ki;
+    const float4 xi = load_target(it, cs, rec, Lc, &ki);
+    __syncthreads();
+    unsigned long long inside = 0;
+    for (int t0 = 0; t0 < total; t0 += kT) {
+        const int cnt = min(kT, total - t0);
+        for (int q = lane; q < cnt; q += kWave) {
+            int kk;
+            tile[q] = staged_source(sg, t0 + q, rec, Lc, zc, &kk);
+            tidx[q] = kk;
+        }
+        __syncthreads();
+        for (int j = 0; j < cnt; ++j) {
+            const float4 pj = tile[j];
+            const float dx = pj.x - xi.x, dy = pj.y - xi.y, dz = pj.z - xi.z;
+            float sp = __builtin_fmaf(dx, dx, P.eps);
+            sp = __builtin_fmaf(dy, dy, sp);
+            sp = __builtin_fmaf(dz, dz, sp);
+            inside += (ki >= 0 && tidx[j] != ki && sp < P.rc2e) ? 1ull : 0ull;
+        }
+        __syncthreads();
+    }
+    // candidates: every source of the window except the target itself
+    unsigned long long cand = ki >= 0 ? (unsigned long long)(total - 1) : 0ull;
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) {
+        inside += __shfl_xor(inside, d);
+        cand += __shfl_xor(cand, d);
+    }
+    if (lane == 0) {
+        atomicAdd(&counts[0], cand);
+        atomicAdd(&counts[1], inside);
+    }
+}
+
+// ------------------------------------------------------------ adjoint
+
+// dL/dx_k = sum_j [f w + 2 f'(s) (d.w) d],  w = m_k g_j - m_j g_k,
+// the transpose of the Jacobian of the pair term applied to the cotangents.
+__global__ __launch_bounds__(kWave) void k_pair_vjp(
+    const WorkItem* __restrict__ items, const int* __restrict__ n_items_dev,
+    const float4* __restrict__ rec, const float4* __restrict__ gsorted,
+    const int* __restrict__ cs, const int* __restrict__ perm, Geom g,
+    PairParams P, double* __restrict__ out_grad) {
+    __shared__ Segments sg;
+    __shared__ float4 tileA[kT];
+    __shared__ float4 tileB[kT];
+    if ((int)blockIdx.x >= *n_items_dev) return;
+    const WorkItem it = items[blockIdx.x];
+    const int lane = threadIdx.x;
+    const float Lc = g.Lc_f;
+    const int total = build_segments(it, cs, g, sg);
+    const int zc = frame_cell(it);
+    int ki;
+    const float4 xk = load_target(it, cs, rec, Lc, &ki);
+    const float4 gk = ki >= 0 ? gsorted[ki] : make_float4(0.f, 0.f, 0.f, 0.f);
+    __syncthreads();
+
+    const float eps = P.eps, rc2e = P.rc2e, alpha = P.alpha, beta = P.beta;
+    const float b0 = P.b[0], b1 = P.b[1], b2 = P.b[2], b3 = P.b[3], b4 = P.b[4],
+                b5 = P.b[5];
+    const float q0 = P.db2[0], q1 = P.db2[1], q2 = P.db2[2], q3 = P.db2[3],
+                q4 = P.db2[4];
+    const float mk = xk.w;
+    float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
+
+    for (int t0 = 0; t0 < total; t0 += kT) {
+        const int cnt = min(kT, total - t0);
+        const int cntp = (cnt + kUnroll - 1) & ~(kUnroll - 1);
+        for (int q = lane; q < cntp; q += kWave) {
+            if (q < cnt) {
+                int kk;
+                tileA[q] = staged_source(sg, t0 + q, rec, Lc, zc, &kk);
+                tileB[q] = gsorted[kk];
+            } else {
+                tileA[q] = pad_source(Lc);
+                tileB[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        }
+        __syncthreads();
+        for (int j0 = 0; j0 < cntp; j0 += kSub) {
+            float tx = 0.f, ty = 0.f, tz = 0.f;
+            const int lim = min(j0 + kSub, cntp);
+            for (int jj = j0; jj < lim; jj += kUnroll) {
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    const float4 pj = tileA[jj + u];
+                    const float4 gj = tileB[jj + u];
+                    const float dx = pj.x - xk.x;
+                    const float dy = pj.y - xk.y;
+                    const float dz = pj.z - xk.z;
+                    float sp = __builtin_fmaf(dx, dx, eps);
+                    sp = __builtin_fmaf(dy, dy, sp);
+                    sp = __builtin_fmaf(dz, dz, sp);
+                    const float y = __builtin_amdgcn_rsqf(sp);
+                    const float t = __builtin_fmaf(sp, alpha, beta);
+                    float p = __builtin_fmaf(b5, t, b4);
+                    p = __builtin_fmaf(p, t, b3);
+                    p = __builtin_fmaf(p, t, b2);
+                    p = __builtin_fmaf(p, t, b1);
+                    p = __builtin_fmaf(p, t, b0);
+                    float q = __builtin_fmaf(q4, t, q3);
+                    q = __builtin_fmaf(q, t, q2);
+                    q = __builtin_fmaf(q, t, q1);
+                    q = __builtin_fmaf(q, t, q0);
+                    const float y2 = y * y;
+                    const float y3 = y2 * y;
+                    const float y5 = y3 * y2;
+                    const bool in = sp < rc2e;
+                    const float f = in ? y3 - p : 0.0f;
+                    const float f2 = in ? __builtin_fmaf(-3.0f, y5, -q) : 0.0f;
+                    const float wx = __builtin_fmaf(mk, gj.x, -(pj.w * gk.x));
+                    const float wy = __builtin_fmaf(mk, gj.y, -(pj.w * gk.y));
+                    const float wz = __builtin_fmaf(mk, gj.z, -(pj.w * gk.z));
+                    float dw = dx * wx;
+                    dw = __builtin_fmaf(dy, wy, dw);
+                    dw = __builtin_fmaf(dz, wz, dw);
+                    const float c = f2 * dw;
+                    tx = __builtin_fmaf(f, wx, tx);
+                    ty = __builtin_fmaf(f, wy, ty);
+                    tz = __builtin_fmaf(f, wz, tz);
+                    tx = __builtin_fmaf(c, dx, tx);
+                    ty = __builtin_fmaf(c, dy, ty);
+                    tz = __builtin_fmaf(c, dz, tz);
+                }
+            }
+            kahan_add(sx, cx, tx);
+            kahan_add(sy, cy, ty);
+            kahan_add(sz, cz, tz);
+        }
+        __syncthreads();
+    }
+    if (ki >= 0) {
+        const int64_t o = 3 * (int64_t)perm[ki];
+        out_grad[o] = (double)sx - (double)cx;
+        out_grad[o + 1] = (double)sy - (double)cy;
+        out_grad[o + 2] = (double)sz - (double)cz;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_pair_force(const WorkItem* items, int max_items,
+                             const int* n_items_dev, const float4* rec,
+                             const int* cell_start, const int* perm, Geom g,
+                             PairParams p, float* out_acc, hipStream_t st) {
+    if (max_items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pair_force, dim3(max_items), dim3(kWave), 0, st, items,
+                       n_items_dev, rec, cell_start, perm, g, p, out_acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_count(const WorkItem* items, int max_items,
+                             const int* n_items_dev, const float4* rec,
+                             const int* cell_start, Geom g, PairParams p,
+                             unsigned long long* counts, hipStream_t st) {
+    if (max_items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pair_count, dim3(max_items), dim3(kWave), 0, st, items,
+                       n_items_dev, rec, cell_start, g, p, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_vjp(const WorkItem* items, int max_items,
+                           const int* n_items_dev, const float4* rec,
+                           const float4* gsorted, const int* cell_start,
+                           const int* perm, Geom g, PairParams p,
+                           double* out_grad, hipStream_t st) {
+    if (max_items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pair_vjp, dim3(max_items), dim3(kWave), 0, st, items,
+                       n_items_dev, rec, gsorted, cell_start, perm, g, p,
+                       out_grad);
+    return hipGetLastError();
+}
+
+}  // namespace hsr

@@ -1,0 +1,75 @@
+"""Stream-kick-stream rollout on the GPU (kick/stream kernels, forward and
+VJP pair kernels, recomputation checkpoints) against the float64 oracle
+rollout (Habib et al. 2012, Sec. II, Eq. 6)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import rollout
+import paper_1211_4864_amd as hsr
+from workloads import make_config
+from conftest import to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def test_kick_stream_kernels(cuda):
+    rng = np.random.default_rng(1)
+    n = 100003
+    x = rng.random((n, 3))
+    v = rng.standard_normal((n, 3))
+    a = rng.standard_normal((n, 3)).astype(np.float32)
+    xt, vt, at = (torch.from_numpy(t).to(cuda) for t in (x, v, a))
+    hsr.kick(vt, at, 0.37)
+    hsr.stream(xt, vt, 0.11, 1.0)
+    ga = hsr.kick_adjoint(vt, 0.5)
+    torch.cuda.synchronize()
+    v1 = v + 0.37 * a.astype(np.float64)
+    x1 = x + 0.11 * v1
+    x1 = x1 - np.floor(x1)
+    assert np.allclose(vt.cpu().numpy(), v1, rtol=4e-16, atol=4e-16)
+    d = xt.cpu().numpy() - x1
+    d -= np.rint(d)
+    assert np.abs(d).max() <= 1e-15
+    assert np.all((xt.cpu().numpy() >= 0) & (xt.cpu().numpy() < 1))
+    assert np.array_equal(ga.cpu().numpy(), (0.5 * vt.cpu().numpy()).astype(np.float32))
+
+
+@pytest.mark.parametrize("name", ["cfg5_64"])
+def test_rollout_and_gradient_vs_oracle(cuda, name):
+    """The one-GPU-share generator (NFW halos, periodic parent with a 3-cell
+    ghost shell, open boundaries) at 64^3, 5 subcycles."""
+    w = make_config(name)
+    n = w.n
+    a0, an0, _ = oracle.force(w.pos, w.mass, w.box, w.r_cut, w.eps, w.poly)
+    h = float(np.sqrt(0.01 * w.cell / np.sqrt((a0 * a0).sum(1).mean())))
+    rng = np.random.default_rng(55)
+    v0 = rng.standard_normal((n, 3)) * 0.01 * w.cell / h
+    gx = rng.standard_normal((n, 3))
+    xr, vr, cps = rollout.sks(w.pos, v0, w.mass, w.box, w.r_cut, w.eps, w.poly, h, 5)
+    gx0_ref, gv0_ref = rollout.sks_vjp(cps, w.mass, w.box, w.r_cut, w.eps, w.poly, h,
+                                       gx, np.zeros_like(gx))
+    pos, mass = to_dev(w, cuda)
+    x0 = pos.clone().requires_grad_(True)
+    v0t = torch.from_numpy(v0).to(cuda).requires_grad_(True)
+    xf, vf = hsr.rollout_sks(x0, v0t, mass, w.box, w.r_cut, w.eps, w.poly, h, 5)
+    loss = (xf * torch.from_numpy(gx).to(cuda)).sum()
+    gx0, gv0 = torch.autograd.grad(loss, (x0, v0t))
+    torch.cuda.synchronize()
+    xf = xf.detach().cpu().numpy()
+    vf = vf.detach().cpu().numpy()
+    # Each force is within 1e-5 max(|a|, 0.1 A) of the float64 one.  Over n_c
+    # subcycles a force error da moves x by at most sum_k (n_c - k + 1/2) h^2 da
+    # = n_c^2/2 h^2 da and v by n_c h da; factor 2 for the drift of the forces.
+    da = 1e-5 * np.maximum(np.linalg.norm(a0, axis=1), 0.1 * an0)
+    dx = np.linalg.norm(xf - xr, axis=1)
+    dv = np.linalg.norm(vf - vr, axis=1)
+    print(f"rollout: max |dx| {dx.max():.3e} (cell {w.cell:.3e}), max |dv| {dv.max():.3e}",
+          flush=True)
+    assert np.all(dx <= 2 * 12.5 * h * h * da + 1e-15)
+    assert np.all(dv <= 2 * 5 * h * da + 1e-15)
+    for got, ref in ((gx0.cpu().numpy(), gx0_ref), (gv0.cpu().numpy(), gv0_ref)):
+        rel = np.abs(got - ref).max() / np.abs(ref).max()
+        print(f"rollout gradient max rel {rel:.3e}", flush=True)
+        assert rel <= 1e-4

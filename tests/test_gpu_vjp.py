@@ -1,0 +1,116 @@
+"""Parity of the HIP adjoint (VJP) kernel and the autograd wrapper with the
+float64 oracle's VJP, and with central finite differences of the oracle's
+forward sum.  Tolerance: |g - g*| <= 1e-4 max(|g*|, 0.1 B), B the summed
+pair-term magnitude of that particle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import binning
+import paper_1211_4864_amd as hsr
+from workloads import make_config, plummer_clustered, cotangent
+from workloads.configs import _finish
+from conftest import to_dev, sample_targets
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+def _clustered(n, grid, n_halo, seed, box=1.0):
+    pos, meta = plummer_clustered(n, seed, n_halo, 0.6, 1.0 / grid)
+    return _finish(f"plummer{n}_g{grid}", pos, seed, grid, meta, box=box)
+
+
+def _gpu_vjp(w, g, device):
+    pos, mass = to_dev(w, device)
+    gt = torch.from_numpy(g).to(device)
+    out = hsr.force_vjp(pos, mass, w.box, w.r_cut, w.eps, w.poly, gt)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def _check(w, g, got, targets=None):
+    ref, bn = oracle.force_vjp(w.pos, w.mass, w.box, w.r_cut, w.eps, w.poly,
+                               g.astype(np.float64), targets=targets)
+    sub = got if targets is None else got[targets]
+    err = oracle.rel_err_floored(sub, ref, bn)
+    print(f"{w.name}: vjp checked={sub.shape[0]} max err={err.max():.3e}", flush=True)
+    assert np.all(np.isfinite(sub))
+    assert err.max() <= TOL
+
+
+@pytest.mark.parametrize("box", [1.0, -1.0])
+def test_vjp_clustered_full(cuda, box):
+    w = _clustered(1 << 16, 32, 40, 21, box=box)
+    g = cotangent(w.n, 4)
+    _check(w, g, _gpu_vjp(w, g, cuda))
+
+
+def test_vjp_cfg4_sampled_and_finite_differences(cuda):
+    """128^3 clustered particles, g ~ N(0,1): VJP vs the oracle VJP on a
+    stratified sample and vs central differences (h = 1e-4 cell, float64 on
+    the oracle) on 64 random particles."""
+    w = make_config("cfg4")
+    g = w.meta["g"]
+    got = _gpu_vjp(w, g, cuda)
+    keys = binning.chaining_mesh(w.pos, w.mass, w.box, w.r_cut)[0]
+    _check(w, g, got, sample_targets(w.n, keys, 2000, seed=4))
+    assert np.abs(got.sum(0)).max() <= 1e-5 * np.abs(got).sum()
+    rng = np.random.default_rng(64)
+    ks = rng.choice(w.n, 64, replace=False)
+    h = 1e-4 * w.cell
+    rc = float(np.float32(w.r_cut))
+    gd = g.astype(np.float64)
+    _, bn = oracle.force_vjp(w.pos, w.mass, w.box, w.r_cut, w.eps, w.poly, gd, targets=ks)
+    checked = 0
+    for t, k in enumerate(ks):
+        d = w.pos - w.pos[k]
+        d -= np.rint(d)
+        r = np.sqrt((d * d).sum(1))
+        r[k] = -1
+        if np.any(np.abs(r - rc) < 3 * h):
+            continue                      # a pair crosses the cut-off within the probe
+        near = np.nonzero(r < rc + 3 * h)[0]
+        idx = np.concatenate([[k], near])
+        for ax in range(3):
+            vals = []
+            for s in (h, -h):
+                p = w.pos.copy()
+                p[k, ax] += s
+                a, _, _ = oracle.force(p, w.mass, w.box, w.r_cut, w.eps, w.poly, targets=idx)
+                vals.append(float(np.sum(gd[idx] * a)))
+            fd = (vals[0] - vals[1]) / (2 * h)
+            assert abs(got[k, ax] - fd) <= TOL * max(abs(fd), 0.1 * bn[t]) + 1e-9 * bn[t]
+            checked += 1
+    assert checked >= 120
+
+
+def test_autograd_matches_vjp_and_dot_product(cuda):
+    w = _clustered(1 << 15, 32, 30, 22)
+    pos, mass = to_dev(w, cuda)
+    pos.requires_grad_(True)
+    acc = hsr.sr_force(pos, mass, w.box, w.r_cut, w.eps, w.poly)
+    g = torch.from_numpy(cotangent(w.n, 5)).to(cuda)
+    (grad,) = torch.autograd.grad((acc * g).sum(), pos)
+    direct = hsr.force_vjp(pos.detach(), mass, w.box, w.r_cut, w.eps, w.poly, g)
+    assert torch.equal(grad, direct)
+    # <g, J v> by a float64 directional difference of the oracle equals <J^T g, v>
+    v = np.random.default_rng(6).standard_normal(w.pos.shape)
+    h = 1e-6 * w.cell
+    gd = g.cpu().numpy().astype(np.float64)
+    ap, _, _ = oracle.force(w.pos + h * v, w.mass, w.box, w.r_cut, w.eps, w.poly)
+    am, _, _ = oracle.force(w.pos - h * v, w.mass, w.box, w.r_cut, w.eps, w.poly)
+    lhs = float(np.sum(gd * (ap - am))) / (2 * h)
+    rhs = float(np.sum(grad.cpu().numpy() * v))
+    assert abs(lhs - rhs) <= 1e-4 * np.abs(grad.cpu().numpy() * v).sum()
+
+
+def test_vjp_linear_in_cotangent_and_reproducible(cuda):
+    w = _clustered(1 << 15, 32, 30, 23)
+    g1 = cotangent(w.n, 7)
+    a = _gpu_vjp(w, g1, cuda)
+    b = _gpu_vjp(w, g1, cuda)
+    assert np.array_equal(a, b)
+    c = _gpu_vjp(w, (2.0 * g1).astype(np.float32), cuda)
+    assert np.array_equal(c, 2.0 * a)            # scaling by 2 is exact in float32

@@ -255,3 +255,33 @@ def test_gaussian_grid_force_against_quadrature():
                             rel_tol=1e-9)
     far = gaussian_grid_force(np.array([100.0]), sig)[0]
     assert math.isclose(far, 100.0 ** -1.5, rel_tol=1e-12)
+
+
+@pytest.mark.parametrize("box", [1.0, -1.0])
+def test_binning_reference_properties(box):
+    """The NumPy chaining mesh: pairs inside r_cut sit in adjacent cells,
+    records rebuild the positions, order is by cell then input index."""
+    from oracle import binning
+    pos, mass, _, fit = _small_case(n=3000, seed=26)
+    keys, perm, cs, rec = binning.chaining_mesh(pos, mass, box, fit.r_cut)
+    N, L = binning.grid(box, fit.r_cut)
+    assert L >= float(np.float32(fit.r_cut))
+    sk = keys[perm]
+    assert np.all(np.diff(sk) >= 0)
+    same = np.diff(sk) == 0
+    assert np.all(np.diff(perm)[same] > 0)            # stable inside a cell
+    assert np.array_equal(np.diff(cs), np.bincount(keys, minlength=N ** 3))
+    c = np.stack([sk // (N * N), (sk // N) % N, sk % N], 1)
+    back = c * L + rec[:, :3].astype(np.float64)
+    assert np.abs(back - pos[perm]).max() <= 2 * L * 2.0 ** -24
+    assert np.array_equal(rec[:, 3], mass[perm])
+    # every pair inside the cut-off lies in adjacent cells (with wrap)
+    d = pos[:, None, :] - pos[None, :, :]
+    if box > 0:
+        d -= np.rint(d)
+    close = np.argwhere((d * d).sum(-1) < float(np.float32(fit.r_cut)) ** 2)
+    ci = np.stack([keys // (N * N), (keys // N) % N, keys % N], 1)
+    dc = np.abs(ci[close[:, 0]] - ci[close[:, 1]])
+    if box > 0:
+        dc = np.minimum(dc, N - dc)
+    assert close.shape[0] > 3000 and dc.max() <= 1
