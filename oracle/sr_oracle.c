@@ -231,11 +231,19 @@ int oracle_force(const double *pos, const float *mass, int64_t n, double box,
  * k (all when targets == NULL).  g: (n,3) float64 cotangents.  out: (nt,3)
  * float64.  bnorm (may be NULL): (nt,) sum_j (|f| + 2|f'| s) |w_kj|, a bound
  * on the summed pair-term magnitudes used to floor relative errors.
+ *
+ * f' jumps at the cut-off (f itself is continuous there), so the VJP is
+ * discontinuous wherever a pair sits on r_cut: an implementation that takes
+ * the cut-off test in a lower precision may count such a pair on the other
+ * side.  amb (may be NULL): (nt,) the summed magnitude (|f| + 2|f'| s)|w| of
+ * the pairs with |s - r_cut^2| <= cut_band * r_cut^2, a bound on how far any
+ * decision for those pairs can move the result.
  */
 int oracle_force_vjp(const double *pos, const float *mass, int64_t n,
                      double box, float r_cut, float eps, const float poly[6],
                      const double *gvec, const int64_t *targets, int64_t nt,
-                     double *out, double *bnorm) {
+                     double *out, double *bnorm, double cut_band,
+                     double *amb) {
     cellgrid g;
     double c[6];
     for (int k = 0; k < 6; ++k) c[k] = (double)poly[k];
@@ -245,7 +253,7 @@ int oracle_force_vjp(const double *pos, const float *mass, int64_t n,
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t t = 0; t < nt; ++t) {
         const int64_t k = targets ? targets[t] : t;
-        double o[3] = {0.0, 0.0, 0.0}, b = 0.0;
+        double o[3] = {0.0, 0.0, 0.0}, b = 0.0, am = 0.0;
         const double mk = (double)mass[k];
         const double gk[3] = {gvec[3 * k], gvec[3 * k + 1], gvec[3 * k + 2]};
         int64_t cells[27];
@@ -257,7 +265,8 @@ int oracle_force_vjp(const double *pos, const float *mass, int64_t n,
                            pos[3 * j + 2] - pos[3 * k + 2]};
             min_image(d, g.periodic, box);
             const double s = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-            if (s < rc2) {
+            const int edge = fabs(s - rc2) <= cut_band * rc2;
+            if (s < rc2 || edge) {
                 const double se = s + e;
                 const double newt = 1.0 / (se * sqrt(se));
                 const double f = newt - horner(c, s);
@@ -267,15 +276,20 @@ int oracle_force_vjp(const double *pos, const float *mass, int64_t n,
                 for (int r = 0; r < 3; ++r)
                     w[r] = mk * gvec[3 * j + r] - mj * gk[r];
                 const double dw = d[0] * w[0] + d[1] * w[1] + d[2] * w[2];
-                for (int r = 0; r < 3; ++r) o[r] += f * w[r] + 2.0 * fp * dw * d[r];
                 const double wn = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
-                b += (fabs(f) + 2.0 * fabs(fp) * s) * wn;
+                const double mag = (fabs(f) + 2.0 * fabs(fp) * s) * wn;
+                if (edge) am += mag;
+                if (s < rc2) {
+                    for (int r = 0; r < 3; ++r) o[r] += f * w[r] + 2.0 * fp * dw * d[r];
+                    b += mag;
+                }
             }
         }
         out[3 * t] = o[0];
         out[3 * t + 1] = o[1];
         out[3 * t + 2] = o[2];
         if (bnorm) bnorm[t] = b;
+        if (amb) amb[t] = am;
     }
     free_grid(&g);
     return 0;

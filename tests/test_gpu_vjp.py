@@ -1,7 +1,11 @@
 """Parity of the HIP adjoint (VJP) kernel and the autograd wrapper with the
 float64 oracle's VJP, and with central finite differences of the oracle's
-forward sum.  Tolerance: |g - g*| <= 1e-4 max(|g*|, 0.1 B), B the summed
-pair-term magnitude of that particle."""
+forward sum.  Tolerance: |g - g*| <= 1e-4 max(|g*|, 0.1 B) + J, B the summed
+pair-term magnitude of that particle and J the magnitude of its pair terms
+within 1e-6 r_cut^2 of the cut-off.  f' jumps at r_cut, so a pair on the cut
+contributes fully or not at all depending on the precision of the cut-off
+test (float32 in the kernel, as the paper's single-precision short-range
+force; float64 in the oracle).  J is zero for almost every particle."""
 import numpy as np
 import pytest
 import torch
@@ -30,13 +34,22 @@ def _gpu_vjp(w, g, device):
     return out.cpu().numpy()
 
 
+BAND = 1e-6
+
+
 def _check(w, g, got, targets=None):
-    ref, bn = oracle.force_vjp(w.pos, w.mass, w.box, w.r_cut, w.eps, w.poly,
-                               g.astype(np.float64), targets=targets)
+    ref, bn, amb = oracle.force_vjp(w.pos, w.mass, w.box, w.r_cut, w.eps, w.poly,
+                                    g.astype(np.float64), targets=targets,
+                                    cut_band=BAND)
     sub = got if targets is None else got[targets]
-    err = oracle.rel_err_floored(sub, ref, bn)
-    print(f"{w.name}: vjp checked={sub.shape[0]} max err={err.max():.3e}", flush=True)
+    dev = np.linalg.norm(sub - ref, axis=1)
+    lim = TOL * np.maximum(np.linalg.norm(ref, axis=1), 0.1 * bn) + amb
+    clean = amb == 0.0
+    err = oracle.rel_err_floored(sub[clean], ref[clean], bn[clean])
+    print(f"{w.name}: vjp checked={sub.shape[0]} (on the cut: {(~clean).sum()}) "
+          f"max err off the cut={err.max():.3e}", flush=True)
     assert np.all(np.isfinite(sub))
+    assert np.all(dev <= lim)
     assert err.max() <= TOL
 
 
@@ -71,8 +84,8 @@ def test_vjp_cfg4_sampled_and_finite_differences(cuda):
         r[k] = -1
         if np.any(np.abs(r - rc) < 3 * h):
             continue                      # a pair crosses the cut-off within the probe
-        near = np.nonzero(r < rc + 3 * h)[0]
-        idx = np.concatenate([[k], near])
+        # L changes only through a_k and the accelerations of k's neighbours
+        idx = np.unique(np.concatenate([[k], np.nonzero(r < rc + 3 * h)[0]]))
         for ax in range(3):
             vals = []
             for s in (h, -h):

@@ -130,3 +130,24 @@ def test_sks_adjoint_matches_finite_differences(oracle_lib):
     fdv = (L(pos, v + eps_fd * dirv) - L(pos, v - eps_fd * dirv)) / (2 * eps_fd)
     assert abs(fdx - np.sum(gx0 * dirx)) <= 1e-6 * np.abs(gx0 * dirx).sum()
     assert abs(fdv - np.sum(gv0 * dirv)) <= 1e-6 * np.abs(gv0 * dirv).sum()
+
+
+def test_vjp_cutoff_band_bounds_the_jump(oracle_lib):
+    """A pair moved across r_cut changes the VJP by at most the band
+    magnitude the oracle reports (f' jumps at the cut-off, f does not)."""
+    fit = fit_fgrid(1.0 / 64.0)
+    rc = float(np.float32(fit.r_cut))
+    mass = np.array([0.3, 0.7], np.float32)
+    g = np.array([[0.2, -1.0, 0.5], [1.0, 0.3, -0.4]])
+    vals = []
+    for sep in (rc * (1 - 1e-9), rc * (1 + 1e-9)):
+        pos = np.array([[0.5, 0.5, 0.5], [0.5 + sep, 0.5, 0.5]])
+        out, bn, amb = oracle.force_vjp(pos, mass, 1.0, fit.r_cut, fit.eps, fit.coeffs,
+                                        g, cut_band=1e-6)
+        _, _, amb0 = oracle.force_vjp(pos, mass, 1.0, fit.r_cut, fit.eps, fit.coeffs,
+                                      g, cut_band=0.0)
+        assert np.all(amb0 == 0.0) and np.all(amb > 0.0)
+        vals.append((out, amb))
+    jump = np.linalg.norm(vals[0][0] - vals[1][0], axis=1)
+    assert np.all(jump > 0.1 * vals[0][1])       # the jump is a full pair term
+    assert np.all(jump <= vals[0][1] * (1 + 1e-6))
