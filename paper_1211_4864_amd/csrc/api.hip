@@ -116,10 +116,9 @@ int make_params(float r_cut, float eps, const float* poly, PairParams* P) {
 
 struct Layout {
     size_t keys_a, vals_a, keys_b, vals_b, counts, hist, scan_tmp, rec,
-        gsorted, col_items, items, items_sorted, bucket_of, buckets, counts64;
+        gsorted, cell_items, items, items_sorted, bucket_of, buckets;
     size_t total;
     int64_t ncell;
-    int ncol;
     int max_items;
     int radix_nb;
 };
@@ -130,11 +129,10 @@ Layout layout_for(int64_t n, const Geom& g) {
     Layout L{};
     const int nn = (int)n;
     L.ncell = (int64_t)g.N * g.N * g.N;
-    L.ncol = g.N * g.N;
-    L.max_items = (int)(std::min<int64_t>(n, L.ncell) + n / kItemI + 1);
+    // a cell of c targets gives floor(c / 64) full items and at most two more
+    L.max_items = (int)(2 * std::min<int64_t>(n, L.ncell) + n / kItemI + 1);
     L.radix_nb = radix_blocks(nn > 0 ? nn : 1);
-    const int64_t scan_n = std::max<int64_t>(
-        {(int64_t)256 * L.radix_nb, L.ncell + 1, (int64_t)L.ncol + 1});
+    const int64_t scan_n = std::max<int64_t>((int64_t)256 * L.radix_nb, L.ncell + 1);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t at = off;
@@ -151,12 +149,11 @@ Layout layout_for(int64_t n, const Geom& g) {
     L.scan_tmp = take(sizeof(int) * scan_tmp_ints((int)scan_n));
     L.rec = take(sizeof(float4) * (size_t)std::max<int64_t>(n, 1));
     L.gsorted = take(sizeof(float4) * (size_t)std::max<int64_t>(n, 1));
-    L.col_items = take(sizeof(int) * (size_t)(L.ncol + 1));
+    L.cell_items = take(sizeof(int) * (size_t)(L.ncell + 1));
     L.items = take(sizeof(WorkItem) * (size_t)L.max_items);
     L.items_sorted = take(sizeof(WorkItem) * (size_t)L.max_items);
     L.bucket_of = take(sizeof(int) * (size_t)L.max_items);
     L.buckets = take(sizeof(int) * 2 * kCostBuckets);
-    L.counts64 = take(sizeof(unsigned long long) * 2);
     L.total = off + 256;   // slack for aligning the base pointer
     return L;
 }
@@ -212,22 +209,21 @@ int bin_impl(const double* pos, const float* mass, int64_t n, const Geom& g,
 // Builds the cost-ordered work list; returns the device counter of items.
 int worklist_impl(const int* cell_start, const Geom& g, const Layout& L,
                   const WorkItem** items_out, const int** n_items_dev) {
-    int* col = ws_at<int>(L.col_items);
+    int* ci = ws_at<int>(L.cell_items);
     WorkItem* items = ws_at<WorkItem>(L.items);
     WorkItem* sorted = ws_at<WorkItem>(L.items_sorted);
     int* bof = ws_at<int>(L.bucket_of);
     int* bc = ws_at<int>(L.buckets);
     int* tmp = ws_at<int>(L.scan_tmp);
-    const int zmax = g.periodic ? std::min(kMaxRun, g.N - 2) : kMaxRun;
-    HIP_TRY(launch_fill_i32(col + L.ncol, 1, 0, g_stream));
-    HIP_TRY(launch_items_count(cell_start, g, zmax, col, g_stream));
-    HIP_TRY(launch_scan_exclusive(col, col, L.ncol + 1, tmp, g_stream));
-    HIP_TRY(launch_items_write(cell_start, g, zmax, col, items, g_stream));
-    HIP_TRY(launch_items_order(items, col + L.ncol, L.max_items, cell_start, g,
-                               bof, bc, bc + kCostBuckets, sorted, tmp,
-                               g_stream));
+    const int nc = (int)L.ncell;
+    HIP_TRY(launch_fill_i32(ci + nc, 1, 0, g_stream));
+    HIP_TRY(launch_items_count(cell_start, g, ci, g_stream));
+    HIP_TRY(launch_scan_exclusive(ci, ci, nc + 1, tmp, g_stream));
+    HIP_TRY(launch_items_write(cell_start, g, ci, items, g_stream));
+    HIP_TRY(launch_items_order(items, ci + nc, L.max_items, cell_start, g, bof,
+                               bc, bc + kCostBuckets, sorted, g_stream));
     *items_out = sorted;
-    *n_items_dev = col + L.ncol;
+    *n_items_dev = ci + nc;
     return HACC_SR_OK;
 }
 

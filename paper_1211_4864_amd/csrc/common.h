@@ -30,20 +30,16 @@ struct PairParams {
     float db2[5];
 };
 
-// One unit of pair-kernel work: up to kItemI target particles drawn from a
-// run of nz consecutive cells of one (x, y) column, starting at cell key0.
+// One unit of pair-kernel work: T = i_count target particles of one cell,
+// processed by one wave with ksplit lanes per target (T * ksplit <= 64).
 struct WorkItem {
     int i_begin;      // first sorted entry of the targets
-    int i_count;      // number of targets (1..kItemI)
-    int key0;         // cell index of the run's first cell
-    int nz;           // cells in the run (1..kMaxRun)
+    int i_count;      // number of targets T (1..kItemI)
+    int key;          // cell index
+    int ksplit;       // lanes per target, a power of two
 };
 
-constexpr int kItemI = 64;     // targets per item: one per lane of a wave
-// Runs are capped at two cells: frame coordinates then stay within two cell
-// sides of the origin (the run's centre), which keeps float32 separations of
-// close pairs as precise as in single-cell frames.
-constexpr int kMaxRun = 2;
+constexpr int kItemI = 64;     // lanes of a wave
 
 // ---- launch wrappers (each defined in the translation unit of its kernels)
 
@@ -66,16 +62,16 @@ hipError_t launch_fill_i32(int* p, int n, int value, hipStream_t st);
 
 // work list (worklist.hip)
 constexpr int kCostBuckets = 128;
-hipError_t launch_items_count(const int* cell_start, Geom g, int zmax,
-                              int* col_items, hipStream_t st);
-hipError_t launch_items_write(const int* cell_start, Geom g, int zmax,
-                              const int* col_off, WorkItem* items,
+hipError_t launch_items_count(const int* cell_start, Geom g, int* cell_items,
+                              hipStream_t st);
+hipError_t launch_items_write(const int* cell_start, Geom g,
+                              const int* cell_off, WorkItem* items,
                               hipStream_t st);
 hipError_t launch_items_order(const WorkItem* items, const int* n_items_dev,
                               int max_items, const int* cell_start, Geom g,
                               int* bucket_of, int* bucket_count,
                               int* bucket_off, WorkItem* items_sorted,
-                              int* scan_tmp, hipStream_t st);
+                              hipStream_t st);
 
 // pair kernels (pair.hip)
 hipError_t launch_pair_force(const WorkItem* items, int max_items,

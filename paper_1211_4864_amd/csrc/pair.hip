@@ -2,25 +2,28 @@
 // Eq. 7):  a_i = sum_j m_j f(s) d,  f(s) = (s + eps)^(-3/2) - poly5(s),
 // zero for s >= r_cut^2, and its vector-Jacobian product.
 //
-// Layout of the work: one wave (64 lanes) per work item.  Each lane owns one
-// target particle in registers; the item's sources (the 27-cell stencil of
-// its cells, read as 9 z-runs of consecutive sorted entries) are staged
-// through LDS in tiles, already shifted into the item's frame (the lower
-// x, y corner of its column and the lower z face of the run's centre cell),
-// and every lane reads each staged source as an LDS broadcast.  This is the GPU analogue of the paper's contiguous,
-// pre-shifted neighbour lists shared by all particles of a leaf (Sec. III,
-// paragraph after Eq. 7): equal-length lists, balanced lanes, no gathers in
-// the inner loop.
+// Layout of the work: one wave (64 lanes) per work item, the targets of one
+// chaining cell.  Each target lives in registers; the item's sources (the
+// 27-cell stencil) are staged through LDS in tiles, already shifted into the
+// cell's frame (origin at its lower corner), and read back as LDS
+// broadcasts.  An item of T targets uses k = 64 / T lanes per target (T and
+// k powers of two except for some remainder items): lane t*k + r takes the
+// sources r, r + k, r + 2k, ... and the k partial sums of a target are
+// combined with wavefront shuffles at the end.  This is the GPU analogue of
+// the paper's contiguous, pre-shifted neighbour lists shared by all particles
+// of a leaf (Sec. III, paragraph after Eq. 7): equal-length lists, balanced
+// lanes, no gathers in the inner loop.
 //
 // Arithmetic: pair terms in float32 on cell-relative coordinates (every
-// coordinate in a frame is within a few cells of the origin, so differences
-// keep their bits); the cut-off is a select, not a branch (the paper's fsel,
-// Sec. III); partial sums over 32 sources are merged into a Kahan-compensated
-// float32 accumulator.  The grid-force polynomial is evaluated by Horner in
-// t = alpha (s + eps) + beta, in [-1, 1] over the cut-off range, whose
-// coefficients the host derives in float64 from the caller's s-basis ones.
-// The library is compiled without floating-point contraction; every fused
-// multiply-add below is written explicitly.
+// frame coordinate lies within one cell side of the cell, so differences of
+// close pairs keep their bits); the cut-off is a select, not a branch (the
+// paper's fsel, Sec. III); each lane accumulates 32 sources in plain float32
+// and merges them into a Kahan-compensated float32 sum; the k lanes of a
+// target are combined in float64.  The grid-force polynomial is evaluated by
+// Horner in t = alpha (s + eps) + beta, in [-1, 1] over the cut-off range,
+// whose coefficients the host derives in float64 from the caller's s-basis
+// ones.  The library is compiled without floating-point contraction; every
+// fused multiply-add below is written explicitly.
 #include "common.h"
 
 namespace hsr {
@@ -28,12 +31,12 @@ namespace hsr {
 namespace {
 
 constexpr int kT = 256;      // sources per LDS tile
-constexpr int kSub = 32;     // sources between compensated merges
-constexpr int kUnroll = 8;   // tile counts are padded to a multiple of this
-constexpr int kSeg = 64;     // segment table entries (one per lane)
+constexpr int kU = 4;        // sources per lane per unrolled step
+constexpr int kMerge = 32;   // sources per lane between compensated merges
+constexpr int kSeg = 32;     // segment table entries (27 stencil cells)
 
-static_assert(9 * (kMaxRun + 2) <= kSeg, "segment table too small");
-static_assert(kItemI == kWave, "one target per lane");
+static_assert(kItemI == kWave, "one item per wave");
+static_assert(kT % (kItemI * kU) == 0, "tile must hold whole steps for any split");
 
 __device__ __forceinline__ int wave_incl_scan(int v) {
     const int lane = threadIdx.x & (kWave - 1);
@@ -52,36 +55,37 @@ __device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
     s = t;
 }
 
-// Coordinate shifted by `cells` cell sides into the item frame.  Targets and
-// sources use this same expression, so a particle meets itself at d = 0.
+// Sum over the k lanes of each target (lanes t*k .. t*k + k - 1), k a power
+// of two; every lane of the group ends with the group total.
+__device__ __forceinline__ double group_sum(double v, int k) {
+    for (int o = 1; o < k; o <<= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Coordinate shifted by `cells` cell sides into the item frame.  Sources are
+// staged with this expression, and cells == 0 leaves a coordinate unchanged,
+// so a particle meets itself at d = 0.
 __device__ __forceinline__ float frame(float rel, int cells, float Lc) {
     return __builtin_fmaf((float)cells, Lc, rel);
 }
 
 struct Segments {
-    int off[kSeg + 1];   // first tile position of each segment; off[kSeg] = total
+    int off[kSeg + 1];   // first tile position of each segment
     int start[kSeg];     // first sorted entry of the segment's cell
-    int code[kSeg];      // (dx+1) | (dy+1) << 4 | zi << 8; zi = window cell 0..nz+1
+    int code[kSeg];      // (dx+1) | (dy+1) << 4 | (dz+1) << 8
 };
 
-// Cell of the run that serves as the frame origin along z (its centre).
-__device__ __forceinline__ int frame_cell(const WorkItem& it) { return it.nz / 2; }
-
-// Builds the segment table of one item (one cell of the stencil per lane)
-// and returns the number of sources.  Must be called by the whole wave.
+// Builds the segment table of one item (one stencil cell per lane) and
+// returns the number of sources.  Must be called by the whole wave.
 __device__ int build_segments(const WorkItem& it, const int* __restrict__ cs,
                               const Geom& g, Segments& sg) {
     const int lane = threadIdx.x;
     const int N = g.N;
-    const int z0 = it.key0 % N;
-    const int col = it.key0 / N;
-    const int cx = col / N, cy = col % N;
-    const int L = it.nz + 2;
+    const int cz = it.key % N, cy = (it.key / N) % N, cx = it.key / (N * N);
     int cnt = 0, start = 0, code = 0;
-    if (lane < 9 * L) {
-        const int ca = lane / L, zi = lane - ca * L;
-        const int a = ca / 3 - 1, b = ca % 3 - 1;
-        int x = cx + a, y = cy + b, z = z0 - 1 + zi;
+    if (lane < 27) {
+        const int a = lane / 9 - 1, b = (lane / 3) % 3 - 1, c = lane % 3 - 1;
+        int x = cx + a, y = cy + b, z = cz + c;
         bool ok = true;
         if (g.periodic) {
             x = x < 0 ? x + N : (x >= N ? x - N : x);
@@ -95,13 +99,15 @@ __device__ int build_segments(const WorkItem& it, const int* __restrict__ cs,
             start = cs[key];
             cnt = cs[key + 1] - start;
         }
-        code = (a + 1) | ((b + 1) << 4) | (zi << 8);
+        code = (a + 1) | ((b + 1) << 4) | ((c + 1) << 8);
     }
     const int incl = wave_incl_scan(cnt);
     const int total = __shfl(incl, kWave - 1);
-    sg.off[lane] = incl - cnt;
-    sg.start[lane] = start;
-    sg.code[lane] = code;
+    if (lane < kSeg) {
+        sg.off[lane] = incl - cnt;
+        sg.start[lane] = start;
+        sg.code[lane] = code;
+    }
     if (lane == 0) sg.off[kSeg] = total;
     return total;
 }
@@ -116,12 +122,10 @@ __device__ __forceinline__ int find_segment(const Segments& sg, int p) {
     return lo;
 }
 
-// Source record at tile position p, shifted into the frame.  Window cell zi
-// lies zi - 1 - zc cells above the frame origin.
+// Source record at tile position p, shifted into the frame.
 __device__ __forceinline__ float4 staged_source(const Segments& sg, int p,
                                                 const float4* __restrict__ rec,
-                                                float Lc, int zc,
-                                                int* sorted_index) {
+                                                float Lc, int* sorted_index) {
     const int s = find_segment(sg, p);
     const int k = sg.start[s] + (p - sg.off[s]);
     const int code = sg.code[s];
@@ -129,33 +133,36 @@ __device__ __forceinline__ float4 staged_source(const Segments& sg, int p,
     *sorted_index = k;
     return make_float4(frame(r.x, (code & 15) - 1, Lc),
                        frame(r.y, ((code >> 4) & 15) - 1, Lc),
-                       frame(r.z, (code >> 8) - 1 - zc, Lc), r.w);
-}
-
-// Target of this lane in the frame: its cell inside the run fixes dz.
-__device__ __forceinline__ float4 load_target(const WorkItem& it,
-                                              const int* __restrict__ cs,
-                                              const float4* __restrict__ rec,
-                                              float Lc, int* k_out) {
-    const int lane = threadIdx.x;
-    float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
-    int k = -1;
-    if (lane < it.i_count) {
-        k = it.i_begin + lane;
-        const float4 r = rec[k];
-        int dz = 0;
-        for (int q = 1; q < it.nz; ++q)
-            if (k >= cs[it.key0 + q]) dz = q;
-        t = make_float4(r.x, r.y, frame(r.z, dz - frame_cell(it), Lc), r.w);
-    }
-    *k_out = k;
-    return t;
+                       frame(r.z, (code >> 8) - 1, Lc), r.w);
 }
 
 // Padding source: zero mass, so it adds exactly zero whether or not it falls
 // inside the cut-off (the select discards any non-finite f beyond it).
 __device__ __forceinline__ float4 pad_source(float Lc) {
     return make_float4(-4.0f * Lc, -4.0f * Lc, -4.0f * Lc, 0.0f);
+}
+
+struct Lanes {
+    int ks;       // lanes per target
+    int r;        // this lane's residue: it takes sources r, r + ks, ...
+    int ki;       // sorted index of this lane's target, -1 if none
+};
+
+__device__ __forceinline__ Lanes lane_map(const WorkItem& it) {
+    Lanes L;
+    L.ks = it.ksplit;
+    const int lk = __ffs(L.ks) - 1;
+    const int t = threadIdx.x >> lk;
+    L.r = threadIdx.x & (L.ks - 1);
+    L.ki = t < it.i_count ? it.i_begin + t : -1;
+    return L;
+}
+
+// Tile positions [0, cntp) with cntp the source count rounded up to whole
+// unrolled steps of every lane (a multiple of ks * kU, at most kT).
+__device__ __forceinline__ int padded_count(int cnt, int ks) {
+    const int step = ks * kU;
+    return (cnt + step - 1) & ~(step - 1);
 }
 
 // ------------------------------------------------------------ forward
@@ -172,9 +179,8 @@ __global__ __launch_bounds__(kWave) void k_pair_force(
     const int lane = threadIdx.x;
     const float Lc = g.Lc_f;
     const int total = build_segments(it, cs, g, sg);
-    const int zc = frame_cell(it);
-    int ki;
-    const float4 xi = load_target(it, cs, rec, Lc, &ki);
+    const Lanes L = lane_map(it);
+    const float4 xi = L.ki >= 0 ? rec[L.ki] : make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
 
     const float eps = P.eps, rc2e = P.rc2e, alpha = P.alpha, beta = P.beta;
@@ -184,19 +190,21 @@ __global__ __launch_bounds__(kWave) void k_pair_force(
 
     for (int t0 = 0; t0 < total; t0 += kT) {
         const int cnt = min(kT, total - t0);
-        const int cntp = (cnt + kUnroll - 1) & ~(kUnroll - 1);
+        const int cntp = padded_count(cnt, L.ks);
         for (int q = lane; q < cntp; q += kWave) {
             int kk;
-            tile[q] = q < cnt ? staged_source(sg, t0 + q, rec, Lc, zc, &kk) : pad_source(Lc);
+            tile[q] = q < cnt ? staged_source(sg, t0 + q, rec, Lc, &kk) : pad_source(Lc);
         }
         __syncthreads();
-        for (int j0 = 0; j0 < cntp; j0 += kSub) {
+        const int nit = cntp / L.ks;          // sources per lane in this tile
+        const float4* src = tile + L.r;
+        for (int j0 = 0; j0 < nit; j0 += kMerge) {
             float tx = 0.f, ty = 0.f, tz = 0.f;
-            const int lim = min(j0 + kSub, cntp);
-            for (int jj = j0; jj < lim; jj += kUnroll) {
+            const int lim = min(j0 + kMerge, nit);
+            for (int jj = j0; jj < lim; jj += kU) {
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    const float4 pj = tile[jj + u];
+                for (int u = 0; u < kU; ++u) {
+                    const float4 pj = src[(jj + u) * L.ks];
                     const float dx = pj.x - xi.x;
                     const float dy = pj.y - xi.y;
                     const float dz = pj.z - xi.z;
@@ -224,11 +232,14 @@ __global__ __launch_bounds__(kWave) void k_pair_force(
         }
         __syncthreads();
     }
-    if (ki >= 0) {
-        const int64_t o = 3 * (int64_t)perm[ki];
-        out_acc[o] = sx - cx;
-        out_acc[o + 1] = sy - cy;
-        out_acc[o + 2] = sz - cz;
+    const double ax = group_sum((double)sx - (double)cx, L.ks);
+    const double ay = group_sum((double)sy - (double)cy, L.ks);
+    const double az = group_sum((double)sz - (double)cz, L.ks);
+    if (L.ki >= 0 && L.r == 0) {
+        const int64_t o = 3 * (int64_t)perm[L.ki];
+        out_acc[o] = (float)ax;
+        out_acc[o + 1] = (float)ay;
+        out_acc[o + 2] = (float)az;
     }
 }
 
@@ -246,31 +257,31 @@ __global__ __launch_bounds__(kWave) void k_pair_count(
     const int lane = threadIdx.x;
     const float Lc = g.Lc_f;
     const int total = build_segments(it, cs, g, sg);
-    const int zc = frame_cell(it);
-    int ki;
-    const float4 xi = load_target(it, cs, rec, Lc, &ki);
+    const Lanes L = lane_map(it);
+    const float4 xi = L.ki >= 0 ? rec[L.ki] : make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
     unsigned long long inside = 0;
     for (int t0 = 0; t0 < total; t0 += kT) {
         const int cnt = min(kT, total - t0);
         for (int q = lane; q < cnt; q += kWave) {
             int kk;
-            tile[q] = staged_source(sg, t0 + q, rec, Lc, zc, &kk);
+            tile[q] = staged_source(sg, t0 + q, rec, Lc, &kk);
             tidx[q] = kk;
         }
         __syncthreads();
-        for (int j = 0; j < cnt; ++j) {
+        for (int j = L.r; j < cnt; j += L.ks) {
             const float4 pj = tile[j];
             const float dx = pj.x - xi.x, dy = pj.y - xi.y, dz = pj.z - xi.z;
             float sp = __builtin_fmaf(dx, dx, P.eps);
             sp = __builtin_fmaf(dy, dy, sp);
             sp = __builtin_fmaf(dz, dz, sp);
-            inside += (ki >= 0 && tidx[j] != ki && sp < P.rc2e) ? 1ull : 0ull;
+            inside += (L.ki >= 0 && tidx[j] != L.ki && sp < P.rc2e) ? 1ull : 0ull;
         }
         __syncthreads();
     }
-    // candidates: every source of the window except the target itself
-    unsigned long long cand = ki >= 0 ? (unsigned long long)(total - 1) : 0ull;
+    // candidates: every source of the stencil except the target itself
+    unsigned long long cand =
+        (L.ki >= 0 && L.r == 0) ? (unsigned long long)(total - 1) : 0ull;
 #pragma unroll
     for (int d = kWave / 2; d >= 1; d >>= 1) {
         inside += __shfl_xor(inside, d);
@@ -299,10 +310,9 @@ __global__ __launch_bounds__(kWave) void k_pair_vjp(
     const int lane = threadIdx.x;
     const float Lc = g.Lc_f;
     const int total = build_segments(it, cs, g, sg);
-    const int zc = frame_cell(it);
-    int ki;
-    const float4 xk = load_target(it, cs, rec, Lc, &ki);
-    const float4 gk = ki >= 0 ? gsorted[ki] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const Lanes L = lane_map(it);
+    const float4 xk = L.ki >= 0 ? rec[L.ki] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 gk = L.ki >= 0 ? gsorted[L.ki] : make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
 
     const float eps = P.eps, rc2e = P.rc2e, alpha = P.alpha, beta = P.beta;
@@ -315,11 +325,11 @@ __global__ __launch_bounds__(kWave) void k_pair_vjp(
 
     for (int t0 = 0; t0 < total; t0 += kT) {
         const int cnt = min(kT, total - t0);
-        const int cntp = (cnt + kUnroll - 1) & ~(kUnroll - 1);
+        const int cntp = padded_count(cnt, L.ks);
         for (int q = lane; q < cntp; q += kWave) {
             if (q < cnt) {
                 int kk;
-                tileA[q] = staged_source(sg, t0 + q, rec, Lc, zc, &kk);
+                tileA[q] = staged_source(sg, t0 + q, rec, Lc, &kk);
                 tileB[q] = gsorted[kk];
             } else {
                 tileA[q] = pad_source(Lc);
@@ -327,14 +337,17 @@ __global__ __launch_bounds__(kWave) void k_pair_vjp(
             }
         }
         __syncthreads();
-        for (int j0 = 0; j0 < cntp; j0 += kSub) {
+        const int nit = cntp / L.ks;
+        const float4* srcA = tileA + L.r;
+        const float4* srcB = tileB + L.r;
+        for (int j0 = 0; j0 < nit; j0 += kMerge) {
             float tx = 0.f, ty = 0.f, tz = 0.f;
-            const int lim = min(j0 + kSub, cntp);
-            for (int jj = j0; jj < lim; jj += kUnroll) {
+            const int lim = min(j0 + kMerge, nit);
+            for (int jj = j0; jj < lim; jj += kU) {
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    const float4 pj = tileA[jj + u];
-                    const float4 gj = tileB[jj + u];
+                for (int u = 0; u < kU; ++u) {
+                    const float4 pj = srcA[(jj + u) * L.ks];
+                    const float4 gj = srcB[(jj + u) * L.ks];
                     const float dx = pj.x - xk.x;
                     const float dy = pj.y - xk.y;
                     const float dz = pj.z - xk.z;
@@ -379,11 +392,14 @@ __global__ __launch_bounds__(kWave) void k_pair_vjp(
         }
         __syncthreads();
     }
-    if (ki >= 0) {
-        const int64_t o = 3 * (int64_t)perm[ki];
-        out_grad[o] = (double)sx - (double)cx;
-        out_grad[o + 1] = (double)sy - (double)cy;
-        out_grad[o + 2] = (double)sz - (double)cz;
+    const double gx = group_sum((double)sx - (double)cx, L.ks);
+    const double gy = group_sum((double)sy - (double)cy, L.ks);
+    const double gz = group_sum((double)sz - (double)cz, L.ks);
+    if (L.ki >= 0 && L.r == 0) {
+        const int64_t o = 3 * (int64_t)perm[L.ki];
+        out_grad[o] = gx;
+        out_grad[o + 1] = gy;
+        out_grad[o + 2] = gz;
     }
 }
 

@@ -1,10 +1,11 @@
-// Work list for the pair kernels.  Each item is one wave's worth of target
-// particles (at most kItemI) taken from a run of consecutive cells along z
-// in one (x, y) column; its sources are the 9 neighbouring columns over the
-// run's z range widened by one cell at each end, i.e. the 27-cell stencil of
-// every cell in the run.  Dense cells are split into several items; sparse
-// cells are merged so that a wave's lanes stay busy.  Items are ordered by
-// decreasing source count so that the longest ones start first.
+// Work list for the pair kernels.  One item is one wave's worth of target
+// particles from a single chaining cell; its sources are the cell's 27-cell
+// stencil.  A cell of c targets yields floor(c/64) items of 64 targets (one
+// per lane) and at most two items for the remainder r = c mod 64: the largest
+// power of two p <= r, and r - p.  An item of T targets runs with k =
+// floor_pow2(64 / T) lanes per target, each lane taking every k-th source,
+// so a power-of-two item keeps all 64 lanes busy whatever its size.  Items
+// are ordered by decreasing cost so that the longest ones start first.
 //
 // This replaces the tree walk that gathers leaf interaction lists in the
 // paper's BG/Q code (Habib et al. 2012, Sec. III, walk minimisation and the
@@ -17,112 +18,82 @@ namespace {
 
 constexpr int kBlock = 256;
 
-__device__ __forceinline__ int cell_count(const int* cs, int key) {
-    return cs[key + 1] - cs[key];
+__device__ __forceinline__ int floor_pow2(int v) {
+    return v <= 0 ? 0 : (1 << (31 - __clz(v)));
 }
 
-// Walks the cells of one column and calls emit(z0, nz, i_begin, i_count) for
-// every item, in increasing z.  Identical in the counting and writing passes.
+// Calls emit(i_offset, count, ksplit) for the items of a cell of c targets.
 template <typename Emit>
-__device__ void walk_column(const int* cs, int col, int N, int zmax, Emit emit) {
-    const int kbase = col * N;
-    bool open = false;
-    int z0 = 0, zlast = 0, run_n = 0;
-    for (int z = 0; z < N; ++z) {
-        const int c = cell_count(cs, kbase + z);
-        if (c == 0) continue;
-        if (c > kItemI) {
-            if (open) {
-                emit(z0, zlast - z0 + 1, cs[kbase + z0], run_n);
-                open = false;
-            }
-            const int start = cs[kbase + z];
-            for (int o = 0; o < c; o += kItemI)
-                emit(z, 1, start + o, min(kItemI, c - o));
-            continue;
-        }
-        if (open && run_n + c <= kItemI && z - z0 + 1 <= zmax) {
-            run_n += c;
-            zlast = z;
-        } else {
-            if (open) emit(z0, zlast - z0 + 1, cs[kbase + z0], run_n);
-            open = true;
-            z0 = z;
-            zlast = z;
-            run_n = c;
-        }
+__device__ void cell_items(int c, Emit emit) {
+    int o = 0;
+    for (; o + kItemI <= c; o += kItemI) emit(o, kItemI, 1);
+    int r = c - o;
+    if (r > 0) {
+        const int p = floor_pow2(r);
+        emit(o, p, kItemI / p);
+        o += p;
+        r -= p;
     }
-    if (open) emit(z0, zlast - z0 + 1, cs[kbase + z0], run_n);
+    if (r > 0) emit(o, r, floor_pow2(kItemI / r));
 }
 
 __global__ __launch_bounds__(kBlock) void k_items_count(
-    const int* __restrict__ cs, int N, int zmax, int* __restrict__ col_items) {
-    const int col = blockIdx.x * kBlock + threadIdx.x;
-    if (col >= N * N) return;
+    const int* __restrict__ cs, int ncell, int* __restrict__ cell_items_out) {
+    const int c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= ncell) return;
     int cnt = 0;
-    walk_column(cs, col, N, zmax, [&](int, int, int, int) { ++cnt; });
-    col_items[col] = cnt;
+    cell_items(cs[c + 1] - cs[c], [&](int, int, int) { ++cnt; });
+    cell_items_out[c] = cnt;
 }
 
 __global__ __launch_bounds__(kBlock) void k_items_write(
-    const int* __restrict__ cs, int N, int zmax, const int* __restrict__ col_off,
+    const int* __restrict__ cs, int ncell, const int* __restrict__ cell_off,
     WorkItem* __restrict__ items) {
-    const int col = blockIdx.x * kBlock + threadIdx.x;
-    if (col >= N * N) return;
-    int k = col_off[col];
-    walk_column(cs, col, N, zmax, [&](int z0, int nz, int ib, int ic) {
+    const int c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= ncell) return;
+    int k = cell_off[c];
+    const int start = cs[c];
+    cell_items(cs[c + 1] - start, [&](int o, int cnt, int ks) {
         WorkItem it;
-        it.i_begin = ib;
-        it.i_count = ic;
-        it.key0 = col * N + z0;
-        it.nz = nz;
+        it.i_begin = start + o;
+        it.i_count = cnt;
+        it.key = c;
+        it.ksplit = ks;
         items[k++] = it;
     });
 }
 
-// Number of source particles in an item's stencil window.
-__device__ int window_sources(const WorkItem& it, const int* cs, const Geom& g) {
+// Number of source particles in the 27-cell stencil of a cell.
+__device__ int window_sources(int key, const int* cs, const Geom& g) {
     const int N = g.N;
-    const int z0 = it.key0 % N;
-    const int col = it.key0 / N;
-    const int cx = col / N, cy = col % N;
+    const int cz = key % N, cy = (key / N) % N, cx = key / (N * N);
     int total = 0;
-    for (int a = -1; a <= 1; ++a) {
-        for (int b = -1; b <= 1; ++b) {
-            int x = cx + a, y = cy + b;
-            if (g.periodic) {
-                x = (x + N) % N;
-                y = (y + N) % N;
-            } else if (x < 0 || x >= N || y < 0 || y >= N) {
-                continue;
-            }
-            const int kb = (x * N + y) * N;
-            int lo = z0 - 1, hi = z0 + it.nz;   // inclusive
-            if (g.periodic) {
-                if (lo < 0) {
-                    total += cs[kb + N] - cs[kb + N - 1];
-                    lo = 0;
+    for (int a = -1; a <= 1; ++a)
+        for (int b = -1; b <= 1; ++b)
+            for (int c = -1; c <= 1; ++c) {
+                int x = cx + a, y = cy + b, z = cz + c;
+                if (g.periodic) {
+                    x = (x + N) % N;
+                    y = (y + N) % N;
+                    z = (z + N) % N;
+                } else if (x < 0 || x >= N || y < 0 || y >= N || z < 0 || z >= N) {
+                    continue;
                 }
-                if (hi >= N) {
-                    total += cs[kb + 1] - cs[kb];
-                    hi = N - 1;
-                }
-            } else {
-                lo = max(lo, 0);
-                hi = min(hi, N - 1);
+                const int kk = (x * N + y) * N + z;
+                total += cs[kk + 1] - cs[kk];
             }
-            total += cs[kb + hi + 1] - cs[kb + lo];
-        }
-    }
     return total;
 }
 
-__device__ __forceinline__ int cost_bucket(int j) {
-    // quarter-octave buckets of the source count, 0 = cheapest
-    const float l = log2f((float)max(j, 1));
+// Quarter-octave buckets of the per-lane source count (the wave's running
+// time), 0 = cheapest.
+__device__ __forceinline__ int cost_bucket(int sources, int ksplit) {
+    const float l = log2f(fmaxf((float)sources / (float)ksplit, 1.0f));
     return min(kCostBuckets - 1, (int)(4.0f * l));
 }
 
+// Per-block histogram of buckets; each block then reserves one range per
+// bucket (one global atomic per bucket and block) in k_items_scatter.
 __global__ __launch_bounds__(kBlock) void k_items_bucket(
     const WorkItem* __restrict__ items, const int* __restrict__ n_items_dev,
     const int* __restrict__ cs, Geom g, int* __restrict__ bucket_of,
@@ -133,7 +104,8 @@ __global__ __launch_bounds__(kBlock) void k_items_bucket(
     const int k = blockIdx.x * kBlock + threadIdx.x;
     const int n_items = *n_items_dev;
     if (k < n_items) {
-        const int b = cost_bucket(window_sources(items[k], cs, g));
+        const WorkItem it = items[k];
+        const int b = cost_bucket(window_sources(it.key, cs, g), it.ksplit);
         bucket_of[k] = b;
         atomicAdd(&h[b], 1);
     }
@@ -142,7 +114,7 @@ __global__ __launch_bounds__(kBlock) void k_items_bucket(
         if (h[q]) atomicAdd(&bucket_count[q], h[q]);
 }
 
-// Offsets in decreasing-cost order; also resets the placement cursors.
+// Offsets in decreasing-cost order.
 __global__ void k_items_bucket_scan(const int* __restrict__ bucket_count,
                                     int* __restrict__ bucket_off) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -157,33 +129,41 @@ __global__ __launch_bounds__(kBlock) void k_items_scatter(
     const WorkItem* __restrict__ items, const int* __restrict__ n_items_dev,
     const int* __restrict__ bucket_of, int* __restrict__ bucket_off,
     WorkItem* __restrict__ out) {
+    __shared__ int h[kCostBuckets];
+    __shared__ int base[kCostBuckets];
+    for (int q = threadIdx.x; q < kCostBuckets; q += kBlock) h[q] = 0;
+    __syncthreads();
     const int k = blockIdx.x * kBlock + threadIdx.x;
-    if (k >= *n_items_dev) return;
+    const bool active = k < *n_items_dev;
+    const int b = active ? bucket_of[k] : 0;
     // Order inside a bucket is arbitrary; results do not depend on it
     // because every item writes only its own targets.
-    const int dst = atomicAdd(&bucket_off[bucket_of[k]], 1);
-    out[dst] = items[k];
+    const int local = active ? atomicAdd(&h[b], 1) : 0;
+    __syncthreads();
+    for (int q = threadIdx.x; q < kCostBuckets; q += kBlock)
+        base[q] = h[q] ? atomicAdd(&bucket_off[q], h[q]) : 0;
+    __syncthreads();
+    if (active) out[base[b] + local] = items[k];
 }
 
 inline int blocks_for(int64_t n, int per) { return (int)((n + per - 1) / per); }
 
 }  // namespace
 
-hipError_t launch_items_count(const int* cell_start, Geom g, int zmax,
-                              int* col_items, hipStream_t st) {
-    const int ncol = g.N * g.N;
-    hipLaunchKernelGGL(k_items_count, dim3(blocks_for(ncol, kBlock)),
-                       dim3(kBlock), 0, st, cell_start, g.N, zmax, col_items);
+hipError_t launch_items_count(const int* cell_start, Geom g, int* cell_items,
+                              hipStream_t st) {
+    const int ncell = g.N * g.N * g.N;
+    hipLaunchKernelGGL(k_items_count, dim3(blocks_for(ncell, kBlock)),
+                       dim3(kBlock), 0, st, cell_start, ncell, cell_items);
     return hipGetLastError();
 }
 
-hipError_t launch_items_write(const int* cell_start, Geom g, int zmax,
-                              const int* col_off, WorkItem* items,
+hipError_t launch_items_write(const int* cell_start, Geom g,
+                              const int* cell_off, WorkItem* items,
                               hipStream_t st) {
-    const int ncol = g.N * g.N;
-    hipLaunchKernelGGL(k_items_write, dim3(blocks_for(ncol, kBlock)),
-                       dim3(kBlock), 0, st, cell_start, g.N, zmax, col_off,
-                       items);
+    const int ncell = g.N * g.N * g.N;
+    hipLaunchKernelGGL(k_items_write, dim3(blocks_for(ncell, kBlock)),
+                       dim3(kBlock), 0, st, cell_start, ncell, cell_off, items);
     return hipGetLastError();
 }
 
@@ -191,7 +171,7 @@ hipError_t launch_items_order(const WorkItem* items, const int* n_items_dev,
                               int max_items, const int* cell_start, Geom g,
                               int* bucket_of, int* bucket_count,
                               int* bucket_off, WorkItem* items_sorted,
-                              int* /*scan_tmp*/, hipStream_t st) {
+                              hipStream_t st) {
     hipError_t e = launch_fill_i32(bucket_count, kCostBuckets, 0, st);
     if (e != hipSuccess) return e;
     const int nb = blocks_for(max_items, kBlock);
