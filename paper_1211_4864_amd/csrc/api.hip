@@ -54,6 +54,13 @@ int timed(int which, F body) {
 
 bool is_fin(double v) { return std::isfinite(v); }
 
+int key_bits(int64_t ncell) {
+    int bits = 0;
+    while (bits < 31 && ((int64_t)1 << bits) < ncell) ++bits;
+    return bits;
+}
+
+
 // Validates (n, box, r_cut) and derives the chaining-mesh geometry.
 int make_geom(int64_t n, double box, float r_cut, Geom* g) {
     if (n < 0 || !is_fin(box) || box == 0.0 || !is_fin(r_cut) || !(r_cut > 0.0f))
@@ -72,6 +79,8 @@ int make_geom(int64_t n, double box, float r_cut, Geom* g) {
     g->box = b;
     g->Lc = b / N;
     g->Lc_f = (float)g->Lc;
+    const int cb = key_bits((int64_t)N * N * N);
+    g->sbits = cb + 6 <= 31 ? 6 : (cb + 3 <= 31 ? 3 : 0);
     return HACC_SR_OK;
 }
 
@@ -102,6 +111,9 @@ int make_params(float r_cut, float eps, const float* poly, PairParams* P) {
     P->beta = beta;
     P->eps = eps;
     P->rc2e = (float)(rc2 + (double)eps);
+    // A margin far above float32 rounding: a culled source fails the
+    // kernel's own cut-off test against every target of the item.
+    P->cull2 = (float)(rc2 * (1.0 + 1.0 / 4096.0));
     for (int m = 0; m < 6; ++m) P->b[m] = (float)b[m];
     // 2 d(poly)/ds = 2 alpha d(poly)/dt
     for (int m = 1; m < 6; ++m) P->db2[m - 1] = (float)(2.0 * (double)alpha * m * b[m]);
@@ -169,11 +181,6 @@ int check_ws(const Layout& L) {
     return HACC_SR_OK;
 }
 
-int key_bits(int64_t ncell) {
-    int bits = 0;
-    while (bits < 31 && ((int64_t)1 << bits) < ncell) ++bits;
-    return bits;
-}
 
 // Bins into the workspace; returns (through the pointers) where cell_start,
 // the permutation and the sorted records ended up.
@@ -191,7 +198,7 @@ int bin_impl(const double* pos, const float* mass, int64_t n, const Geom& g,
     HIP_TRY(launch_fill_i32(cell_start, ncp, 0, g_stream));
     HIP_TRY(launch_cell_keys(pos, nn, g, ka, va, cell_start, g_stream));
     HIP_TRY(launch_scan_exclusive(cell_start, cell_start, ncp, tmp, g_stream));
-    const int passes = (key_bits(L.ncell) + 7) / 8;
+    const int passes = (key_bits(L.ncell) + g.sbits + 7) / 8;
     for (int p = 0; p < passes; ++p) {
         HIP_TRY(launch_radix_pass(ka, va, kb, vb, nn, 8 * p, hist, tmp, g_stream));
         std::swap(ka, kb);

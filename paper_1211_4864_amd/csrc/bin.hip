@@ -1,6 +1,9 @@
 // Chaining-mesh binning: cell keys and occupancy histogram, exclusive prefix
-// scan, stable LSD radix scatter (so particles keep their input order inside
-// a cell), and the gather of cell-relative float32 records.
+// scan, stable LSD radix scatter, and the gather of cell-relative float32
+// records.  The sort key is the cell index followed by the Morton code of the
+// particle's sub-cell (4^3 per cell when the key has room), so a cell's
+// particles are grouped spatially and, within a sub-cell, keep their input
+// order: the binning is deterministic.
 //
 // The chaining mesh is the cell list of the particle-particle part of a
 // P^3M code (Habib et al. 2012, Sec. II); cells are at least r_cut wide so
@@ -52,6 +55,14 @@ __device__ __forceinline__ int axis_cell(double x, const Geom& g, double* xw) {
     return c;
 }
 
+// Sub-cell index along one axis, 0..S-1, of a coordinate in its cell.
+__device__ __forceinline__ int axis_sub(double xw, int c, const Geom& g, int S) {
+    const double t = floor((xw - (double)c * g.Lc) / g.Lc * (double)S);
+    if (!(t >= 0.0)) return 0;
+    if (!(t <= (double)(S - 1))) return S - 1;
+    return (int)t;
+}
+
 __global__ __launch_bounds__(kBlock) void k_cell_keys(
     const double* __restrict__ pos, int n, Geom g, int* __restrict__ keys,
     int* __restrict__ vals, int* __restrict__ counts) {
@@ -59,12 +70,23 @@ __global__ __launch_bounds__(kBlock) void k_cell_keys(
     const bool active = i < n;
     int key = 0;
     if (active) {
-        double xw;
+        double xw, yw, zw;
         const int cx = axis_cell(pos[3 * (int64_t)i], g, &xw);
-        const int cy = axis_cell(pos[3 * (int64_t)i + 1], g, &xw);
-        const int cz = axis_cell(pos[3 * (int64_t)i + 2], g, &xw);
+        const int cy = axis_cell(pos[3 * (int64_t)i + 1], g, &yw);
+        const int cz = axis_cell(pos[3 * (int64_t)i + 2], g, &zw);
         key = (cx * g.N + cy) * g.N + cz;
-        keys[i] = key;
+        int code = 0;
+        const int levels = g.sbits / 3;
+        if (levels > 0) {
+            const int S = 1 << levels;
+            const int sx = axis_sub(xw, cx, g, S);
+            const int sy = axis_sub(yw, cy, g, S);
+            const int sz = axis_sub(zw, cz, g, S);
+            for (int b = 0; b < levels; ++b)
+                code |= (((sx >> b) & 1) << (3 * b + 2)) |
+                        (((sy >> b) & 1) << (3 * b + 1)) | (((sz >> b) & 1) << (3 * b));
+        }
+        keys[i] = (key << g.sbits) | code;
         vals[i] = i;
     }
     // Histogram with the first lane's cell aggregated over the wave: inputs
@@ -247,7 +269,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_records(
     const int k = blockIdx.x * kBlock + threadIdx.x;
     if (k >= n) return;
     const int i = perm[k];
-    const int key = keys[k];
+    const int key = keys[k] >> g.sbits;
     const int cz = key % g.N;
     const int cy = (key / g.N) % g.N;
     const int cx = key / (g.N * g.N);

@@ -16,6 +16,7 @@ struct Geom {
     double box;       // |box|
     double Lc;        // cell side, float64
     float Lc_f;       // cell side rounded to float32 (frame shifts)
+    int sbits;        // sub-cell bits of the sort key: 6 (4^3 sub-cells), 3 or 0
 };
 
 // Pair-kernel constants derived on the host from (r_cut, eps, poly).
@@ -26,6 +27,8 @@ struct PairParams {
     float alpha, beta;
     float eps;
     float rc2e;       // float32(r_cut^2 + eps): cut-off test on s + eps
+    float cull2;      // float32(r_cut^2 (1 + 2^-12)): staging drops sources
+                      // at least this far (squared) from the target box
     float b[6];
     float db2[5];
 };

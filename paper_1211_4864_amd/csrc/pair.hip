@@ -6,8 +6,12 @@
 // chaining cell.  Each target lives in registers; the item's sources (the
 // 27-cell stencil) are staged through LDS in tiles, already shifted into the
 // cell's frame (origin at its lower corner), and read back as LDS
-// broadcasts.  An item of T targets uses k = 64 / T lanes per target (T and
-// k powers of two except for some remainder items): lane t*k + r takes the
+// broadcasts.  Staging drops every source farther than r_cut from the
+// bounding box of the item's targets (they could only add zeros), and loads
+// the next tile's sources into registers before the current tile is
+// evaluated, so the global-memory latency overlaps the pair arithmetic.  An
+// item of T targets uses k = 64 / T lanes per target (T and k powers of two
+// except for some remainder items): lane t*k + r takes the
 // sources r, r + k, r + 2k, ... and the k partial sums of a target are
 // combined with wavefront shuffles at the end.  This is the GPU analogue of
 // the paper's contiguous, pre-shifted neighbour lists shared by all particles
@@ -122,18 +126,107 @@ __device__ __forceinline__ int find_segment(const Segments& sg, int p) {
     return lo;
 }
 
-// Source record at tile position p, shifted into the frame.
-__device__ __forceinline__ float4 staged_source(const Segments& sg, int p,
-                                                const float4* __restrict__ rec,
-                                                float Lc, int* sorted_index) {
+// Window position p -> sorted entry and stencil code of its cell.
+__device__ __forceinline__ int window_entry(const Segments& sg, int p, int* code) {
     const int s = find_segment(sg, p);
-    const int k = sg.start[s] + (p - sg.off[s]);
-    const int code = sg.code[s];
-    const float4 r = rec[k];
-    *sorted_index = k;
+    *code = sg.code[s];
+    return sg.start[s] + (p - sg.off[s]);
+}
+
+// Record shifted from its own cell into the item frame.
+__device__ __forceinline__ float4 shift_into_frame(float4 r, int code, float Lc) {
     return make_float4(frame(r.x, (code & 15) - 1, Lc),
                        frame(r.y, ((code >> 4) & 15) - 1, Lc),
                        frame(r.z, (code >> 8) - 1, Lc), r.w);
+}
+
+constexpr int kPer = kT / kWave;   // window positions per lane per tile
+
+// One tile's worth of window positions, loaded into registers: lane l holds
+// positions cursor + u * 64 + l, u < kPer.
+template <bool WithG>
+struct Round {
+    float4 v[kPer];
+    float4 g[WithG ? kPer : 1];
+    int code[kPer];
+    int k[kPer];     // sorted entry, -1 past the end of the window
+};
+
+template <bool WithG>
+__device__ __forceinline__ void load_round(const Segments& sg, int cursor,
+                                           int total,
+                                           const float4* __restrict__ rec,
+                                           const float4* __restrict__ gsorted,
+                                           Round<WithG>& R) {
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int p = cursor + u * kWave + (int)threadIdx.x;
+        R.k[u] = -1;
+        R.code[u] = 0;
+        if (p < total) {
+            R.k[u] = window_entry(sg, p, &R.code[u]);
+            R.v[u] = rec[R.k[u]];
+            if (WithG) R.g[u] = gsorted[R.k[u]];
+        }
+    }
+}
+
+// Squared distance from a point to the box [lo, hi].
+__device__ __forceinline__ float box_gap2(float4 s, float4 lo, float4 hi) {
+    const float gx = fmaxf(fmaxf(lo.x - s.x, s.x - hi.x), 0.0f);
+    const float gy = fmaxf(fmaxf(lo.y - s.y, s.y - hi.y), 0.0f);
+    const float gz = fmaxf(fmaxf(lo.z - s.z, s.z - hi.z), 0.0f);
+    float d = gx * gx;
+    d = __builtin_fmaf(gy, gy, d);
+    return __builtin_fmaf(gz, gz, d);
+}
+
+// Writes the sources of a round that lie within the cull distance of the
+// target box into the tile, in window order; returns their number.
+template <bool WithG>
+__device__ __forceinline__ int compact_round(const Round<WithG>& R, float4 lo,
+                                             float4 hi, float cull2, float Lc,
+                                             float4* tileA, float4* tileB,
+                                             int* tidx) {
+    const uint64_t lt = threadIdx.x == 0 ? 0ull : (~0ull >> (64 - threadIdx.x));
+    int fill = 0;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        bool keep = R.k[u] >= 0;
+        float4 sv = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (keep) {
+            sv = shift_into_frame(R.v[u], R.code[u], Lc);
+            keep = box_gap2(sv, lo, hi) < cull2;
+        }
+        const uint64_t m = __ballot(keep);
+        if (keep) {
+            const int pos = fill + __popcll(m & lt);
+            tileA[pos] = sv;
+            if (WithG) tileB[pos] = R.g[u];
+            if (tidx) tidx[pos] = R.k[u];
+        }
+        fill += __popcll(m);
+    }
+    return fill;
+}
+
+// Bounding box of the item's targets (lanes without a target hold none).
+__device__ __forceinline__ void target_box(float4 x, bool valid, float4* lo,
+                                           float4* hi) {
+    const float inf = __builtin_huge_valf();
+    float a = valid ? x.x : inf, b = valid ? x.y : inf, c = valid ? x.z : inf;
+    float d = valid ? x.x : -inf, e = valid ? x.y : -inf, f = valid ? x.z : -inf;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        a = fminf(a, __shfl_xor(a, o));
+        b = fminf(b, __shfl_xor(b, o));
+        c = fminf(c, __shfl_xor(c, o));
+        d = fmaxf(d, __shfl_xor(d, o));
+        e = fmaxf(e, __shfl_xor(e, o));
+        f = fmaxf(f, __shfl_xor(f, o));
+    }
+    *lo = make_float4(a, b, c, 0.f);
+    *hi = make_float4(d, e, f, 0.f);
 }
 
 // Padding source: zero mass, so it adds exactly zero whether or not it falls
@@ -181,6 +274,8 @@ __global__ __launch_bounds__(kWave) void k_pair_force(
     const int total = build_segments(it, cs, g, sg);
     const Lanes L = lane_map(it);
     const float4 xi = L.ki >= 0 ? rec[L.ki] : make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 lo, hi;
+    target_box(xi, L.ki >= 0, &lo, &hi);
     __syncthreads();
 
     const float eps = P.eps, rc2e = P.rc2e, alpha = P.alpha, beta = P.beta;
@@ -188,14 +283,14 @@ __global__ __launch_bounds__(kWave) void k_pair_force(
                 b5 = P.b[5];
     float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
 
-    for (int t0 = 0; t0 < total; t0 += kT) {
-        const int cnt = min(kT, total - t0);
+    Round<false> R;
+    load_round(sg, 0, total, rec, rec, R);
+    for (int cursor = 0; cursor < total; cursor += kT) {
+        const int cnt = compact_round(R, lo, hi, P.cull2, Lc, tile, tile, nullptr);
         const int cntp = padded_count(cnt, L.ks);
-        for (int q = lane; q < cntp; q += kWave) {
-            int kk;
-            tile[q] = q < cnt ? staged_source(sg, t0 + q, rec, Lc, &kk) : pad_source(Lc);
-        }
+        for (int q = cnt + lane; q < cntp; q += kWave) tile[q] = pad_source(Lc);
         __syncthreads();
+        if (cursor + kT < total) load_round(sg, cursor + kT, total, rec, rec, R);
         const int nit = cntp / L.ks;          // sources per lane in this tile
         const float4* src = tile + L.r;
         for (int j0 = 0; j0 < nit; j0 += kMerge) {
@@ -245,6 +340,8 @@ __global__ __launch_bounds__(kWave) void k_pair_force(
 
 // ------------------------------------------------------------ pair counts
 
+// Counts the pairs the force kernel evaluates (sources that survive the
+// staging cull, minus the target itself) and those inside the cut-off.
 __global__ __launch_bounds__(kWave) void k_pair_count(
     const WorkItem* __restrict__ items, const int* __restrict__ n_items_dev,
     const float4* __restrict__ rec, const int* __restrict__ cs, Geom g,
@@ -254,20 +351,20 @@ __global__ __launch_bounds__(kWave) void k_pair_count(
     __shared__ int tidx[kT];
     if ((int)blockIdx.x >= *n_items_dev) return;
     const WorkItem it = items[blockIdx.x];
-    const int lane = threadIdx.x;
     const float Lc = g.Lc_f;
     const int total = build_segments(it, cs, g, sg);
     const Lanes L = lane_map(it);
     const float4 xi = L.ki >= 0 ? rec[L.ki] : make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 lo, hi;
+    target_box(xi, L.ki >= 0, &lo, &hi);
     __syncthreads();
     unsigned long long inside = 0;
-    for (int t0 = 0; t0 < total; t0 += kT) {
-        const int cnt = min(kT, total - t0);
-        for (int q = lane; q < cnt; q += kWave) {
-            int kk;
-            tile[q] = staged_source(sg, t0 + q, rec, Lc, &kk);
-            tidx[q] = kk;
-        }
+    int kept = 0;
+    Round<false> R;
+    for (int cursor = 0; cursor < total; cursor += kT) {
+        load_round(sg, cursor, total, rec, rec, R);
+        const int cnt = compact_round(R, lo, hi, P.cull2, Lc, tile, tile, tidx);
+        kept += cnt;
         __syncthreads();
         for (int j = L.r; j < cnt; j += L.ks) {
             const float4 pj = tile[j];
@@ -279,15 +376,15 @@ __global__ __launch_bounds__(kWave) void k_pair_count(
         }
         __syncthreads();
     }
-    // candidates: every source of the stencil except the target itself
+    // evaluated candidates: every kept source except the target itself
     unsigned long long cand =
-        (L.ki >= 0 && L.r == 0) ? (unsigned long long)(total - 1) : 0ull;
+        (L.ki >= 0 && L.r == 0) ? (unsigned long long)(kept - 1) : 0ull;
 #pragma unroll
     for (int d = kWave / 2; d >= 1; d >>= 1) {
         inside += __shfl_xor(inside, d);
         cand += __shfl_xor(cand, d);
     }
-    if (lane == 0) {
+    if (threadIdx.x == 0) {
         atomicAdd(&counts[0], cand);
         atomicAdd(&counts[1], inside);
     }
@@ -313,6 +410,8 @@ __global__ __launch_bounds__(kWave) void k_pair_vjp(
     const Lanes L = lane_map(it);
     const float4 xk = L.ki >= 0 ? rec[L.ki] : make_float4(0.f, 0.f, 0.f, 0.f);
     const float4 gk = L.ki >= 0 ? gsorted[L.ki] : make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 lo, hi;
+    target_box(xk, L.ki >= 0, &lo, &hi);
     __syncthreads();
 
     const float eps = P.eps, rc2e = P.rc2e, alpha = P.alpha, beta = P.beta;
@@ -323,20 +422,17 @@ __global__ __launch_bounds__(kWave) void k_pair_vjp(
     const float mk = xk.w;
     float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
 
-    for (int t0 = 0; t0 < total; t0 += kT) {
-        const int cnt = min(kT, total - t0);
+    Round<true> R;
+    load_round(sg, 0, total, rec, gsorted, R);
+    for (int cursor = 0; cursor < total; cursor += kT) {
+        const int cnt = compact_round(R, lo, hi, P.cull2, Lc, tileA, tileB, nullptr);
         const int cntp = padded_count(cnt, L.ks);
-        for (int q = lane; q < cntp; q += kWave) {
-            if (q < cnt) {
-                int kk;
-                tileA[q] = staged_source(sg, t0 + q, rec, Lc, &kk);
-                tileB[q] = gsorted[kk];
-            } else {
-                tileA[q] = pad_source(Lc);
-                tileB[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-            }
+        for (int q = cnt + lane; q < cntp; q += kWave) {
+            tileA[q] = pad_source(Lc);
+            tileB[q] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
         __syncthreads();
+        if (cursor + kT < total) load_round(sg, cursor + kT, total, rec, gsorted, R);
         const int nit = cntp / L.ks;
         const float4* srcA = tileA + L.r;
         const float4* srcB = tileB + L.r;

@@ -43,7 +43,7 @@ def _clustered(n, grid, n_halo, seed, box=1.0):
 
 
 @pytest.mark.parametrize("box", [1.0, -1.0])
-def test_binning_matches_stable_sort(cuda, box):
+def test_binning_matches_reference_order(cuda, box):
     w = _clustered(1 << 16, 32, 40, 7, box=box)
     pos, mass = to_dev(w, cuda)
     cs, perm, rec = hsr.bin(pos, mass, w.box, w.r_cut)
@@ -183,5 +183,7 @@ def test_pair_counts(cuda):
     occ = np.diff(cs).reshape(N, N, N)
     stencil = sum(np.roll(occ, (a, b, c), (0, 1, 2)) for a in (-1, 0, 1)
                   for b in (-1, 0, 1) for c in (-1, 0, 1))
-    lower = int((occ * (stencil - 1)).sum())
-    assert lower <= cand <= 3 * lower and cand >= inside
+    # the kernel evaluates the 27-cell stencil minus the sources the staging
+    # cull proves to be out of range
+    stencil_pairs = int((occ * (stencil - 1)).sum())
+    assert inside <= cand <= stencil_pairs

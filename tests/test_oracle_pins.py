@@ -268,8 +268,15 @@ def test_binning_reference_properties(box):
     assert L >= float(np.float32(fit.r_cut))
     sk = keys[perm]
     assert np.all(np.diff(sk) >= 0)
-    same = np.diff(sk) == 0
-    assert np.all(np.diff(perm)[same] > 0)            # stable inside a cell
+    # inside a cell: sub-cells in Morton order, input order inside a sub-cell
+    lev = binning.sub_levels(N)
+    rel = rec[:, :3].astype(np.float64) / L * (1 << lev)
+    s3 = np.clip(np.floor(rel), 0, (1 << lev) - 1).astype(np.int64)
+    same_cell = np.diff(sk) == 0
+    sub_id = s3[:, 0] * 100 + s3[:, 1] * 10 + s3[:, 2]
+    same_sub = same_cell & (np.diff(sub_id) == 0)
+    assert np.all(np.diff(perm)[same_sub] > 0)
+    assert lev == 2
     assert np.array_equal(np.diff(cs), np.bincount(keys, minlength=N ** 3))
     c = np.stack([sk // (N * N), (sk // N) % N, sk % N], 1)
     back = c * L + rec[:, :3].astype(np.float64)
