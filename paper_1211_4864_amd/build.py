@@ -38,7 +38,8 @@ def sources():
 
 def build(verbose: bool = False, extra_flags=(), out: str = LIB) -> str:
     """Compile every csrc/*.hip into one shared library and return its path."""
-    build_dir = os.path.join(HERE, "_build")
+    tag = os.path.splitext(os.path.basename(out))[0]
+    build_dir = os.path.join(os.path.dirname(out), "_build", tag)
     os.makedirs(build_dir, exist_ok=True)
     objs = []
     for src in sources():

@@ -34,10 +34,43 @@ namespace hsr {
 
 namespace {
 
-constexpr int kT = 256;      // sources per LDS tile
-constexpr int kU = 4;        // sources per lane per unrolled step
-constexpr int kMerge = 32;   // sources per lane between compensated merges
-constexpr int kSeg = 32;     // segment table entries (27 stencil cells)
+// Tuning knobs (build-time): tile size, unroll, merge interval, whether the
+// next tile is loaded into registers during the current one, and the minimum
+// number of waves per SIMD the register allocation must allow.  The defaults
+// are the fastest measured on MI355X for the 256^3 clustered workload: high
+// occupancy hides the staging latency better than register prefetch.
+#ifndef HSR_TILE
+#define HSR_TILE 256
+#endif
+#ifndef HSR_UNROLL
+#define HSR_UNROLL 2
+#endif
+#ifndef HSR_MERGE
+#define HSR_MERGE 32
+#endif
+#ifndef HSR_MIN_WAVES
+#define HSR_MIN_WAVES 8
+#endif
+#ifndef HSR_PREFETCH
+#define HSR_PREFETCH 0
+#endif
+#ifndef HSR_VJP_TILE
+#define HSR_VJP_TILE 128
+#endif
+#ifndef HSR_VJP_MIN_WAVES
+#define HSR_VJP_MIN_WAVES 6
+#endif
+#ifndef HSR_VJP_UNROLL
+#define HSR_VJP_UNROLL 2
+#endif
+#ifndef HSR_VJP_PREFETCH
+#define HSR_VJP_PREFETCH 0
+#endif
+
+constexpr int kT = HSR_TILE;       // sources per LDS tile
+constexpr int kU = HSR_UNROLL;     // sources per lane per unrolled step
+constexpr int kMerge = HSR_MERGE;  // sources per lane between compensated merges
+constexpr int kSeg = 32;           // segment table entries (27 stencil cells)
 
 static_assert(kItemI == kWave, "one item per wave");
 static_assert(kT % (kItemI * kU) == 0, "tile must hold whole steps for any split");
@@ -57,6 +90,14 @@ __device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
     const float t = s + y;
     c = (t - s) - y;
     s = t;
+}
+
+// Wave-uniform values kept in scalar registers.
+__device__ __forceinline__ float uniform(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ float4 uniform(float4 v) {
+    return make_float4(uniform(v.x), uniform(v.y), uniform(v.z), uniform(v.w));
 }
 
 // Sum over the k lanes of each target (lanes t*k .. t*k + k - 1), k a power
@@ -140,24 +181,28 @@ __device__ __forceinline__ float4 shift_into_frame(float4 r, int code, float Lc)
                        frame(r.z, (code >> 8) - 1, Lc), r.w);
 }
 
-constexpr int kPer = kT / kWave;   // window positions per lane per tile
+constexpr int kVT = HSR_VJP_TILE;     // sources per LDS tile of the VJP kernel
+constexpr int kVU = HSR_VJP_UNROLL;   // VJP sources per lane per unrolled step
+static_assert(kVT % (kItemI * kVU) == 0, "VJP tile must hold whole steps");
 
 // One tile's worth of window positions, loaded into registers: lane l holds
-// positions cursor + u * 64 + l, u < kPer.
-template <bool WithG>
+// positions cursor + u * 64 + l, u < TILE / 64.
+template <bool WithG, int TILE>
 struct Round {
+    static constexpr int kPer = TILE / kWave;
     float4 v[kPer];
     float4 g[WithG ? kPer : 1];
     int code[kPer];
     int k[kPer];     // sorted entry, -1 past the end of the window
 };
 
-template <bool WithG>
+template <bool WithG, int TILE>
 __device__ __forceinline__ void load_round(const Segments& sg, int cursor,
                                            int total,
                                            const float4* __restrict__ rec,
                                            const float4* __restrict__ gsorted,
-                                           Round<WithG>& R) {
+                                           Round<WithG, TILE>& R) {
+    constexpr int kPer = TILE / kWave;
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
         const int p = cursor + u * kWave + (int)threadIdx.x;
@@ -183,13 +228,17 @@ __device__ __forceinline__ float box_gap2(float4 s, float4 lo, float4 hi) {
 
 // Writes the sources of a round that lie within the cull distance of the
 // target box into the tile, in window order; returns their number.
-template <bool WithG>
-__device__ __forceinline__ int compact_round(const Round<WithG>& R, float4 lo,
+// *mixed is set when a kept source's mass differs from mref.
+template <bool WithG, int TILE>
+__device__ __forceinline__ int compact_round(const Round<WithG, TILE>& R, float4 lo,
                                              float4 hi, float cull2, float Lc,
-                                             float4* tileA, float4* tileB,
-                                             int* tidx) {
+                                             float mref, float4* tileA,
+                                             float4* tileB, int* tidx,
+                                             bool* mixed) {
+    constexpr int kPer = TILE / kWave;
     const uint64_t lt = threadIdx.x == 0 ? 0ull : (~0ull >> (64 - threadIdx.x));
     int fill = 0;
+    bool other = false;
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
         bool keep = R.k[u] >= 0;
@@ -197,6 +246,7 @@ __device__ __forceinline__ int compact_round(const Round<WithG>& R, float4 lo,
         if (keep) {
             sv = shift_into_frame(R.v[u], R.code[u], Lc);
             keep = box_gap2(sv, lo, hi) < cull2;
+            other |= keep && sv.w != mref;
         }
         const uint64_t m = __ballot(keep);
         if (keep) {
@@ -207,6 +257,7 @@ __device__ __forceinline__ int compact_round(const Round<WithG>& R, float4 lo,
         }
         fill += __popcll(m);
     }
+    *mixed = __ballot(other) != 0ull;
     return fill;
 }
 
@@ -225,14 +276,16 @@ __device__ __forceinline__ void target_box(float4 x, bool valid, float4* lo,
         e = fmaxf(e, __shfl_xor(e, o));
         f = fmaxf(f, __shfl_xor(f, o));
     }
-    *lo = make_float4(a, b, c, 0.f);
-    *hi = make_float4(d, e, f, 0.f);
+    // every lane holds the wave's result: keep it in scalar registers
+    *lo = uniform(make_float4(a, b, c, 0.f));
+    *hi = uniform(make_float4(d, e, f, 0.f));
 }
 
-// Padding source: zero mass, so it adds exactly zero whether or not it falls
-// inside the cut-off (the select discards any non-finite f beyond it).
-__device__ __forceinline__ float4 pad_source(float Lc) {
-    return make_float4(-4.0f * Lc, -4.0f * Lc, -4.0f * Lc, 0.0f);
+// Padding source: zero mass, two cell sides below the target box on every
+// axis, so s >= 12 Lc^2 > r_cut^2 for every target and the cut-off select
+// zeroes it on both the general and the equal-mass paths.
+__device__ __forceinline__ float4 pad_source(float4 lo, float Lc) {
+    return make_float4(lo.x - 2.0f * Lc, lo.y - 2.0f * Lc, lo.z - 2.0f * Lc, 0.0f);
 }
 
 struct Lanes {
@@ -252,15 +305,73 @@ __device__ __forceinline__ Lanes lane_map(const WorkItem& it) {
 }
 
 // Tile positions [0, cntp) with cntp the source count rounded up to whole
-// unrolled steps of every lane (a multiple of ks * kU, at most kT).
-__device__ __forceinline__ int padded_count(int cnt, int ks) {
-    const int step = ks * kU;
+// unrolled steps of every lane (a multiple of ks * kU, at most the tile).
+__device__ __forceinline__ int padded_count(int cnt, int ks, int unroll = kU) {
+    const int step = ks * unroll;
     return (cnt + step - 1) & ~(step - 1);
 }
 
 // ------------------------------------------------------------ forward
 
-__global__ __launch_bounds__(kWave) void k_pair_force(
+struct ForceConsts {
+    float eps, rc2e, alpha, beta, b0, b1, b2, b3, b4, b5;
+};
+
+__device__ __forceinline__ ForceConsts force_consts(const PairParams& P) {
+    return ForceConsts{P.eps, P.rc2e, P.alpha, P.beta, P.b[0],
+                       P.b[1], P.b[2],  P.b[3], P.b[4], P.b[5]};
+}
+
+// Evaluates the tile for this lane: nit sources src[j * stride], j < nit
+// (stride = KS when KS > 0, else ks), merging every kMerge partial sums
+// into the compensated accumulators.  UNI: every source and target has mass
+// mref, so the mass multiplies the partial sums instead of every pair.
+template <int KS, bool UNI>
+__device__ __forceinline__ void force_tile(const float4* __restrict__ src,
+                                           int ks, int nit, float4 xi,
+                                           const ForceConsts& c, float mref,
+                                           float* s, float* cc) {
+    const int st = KS > 0 ? KS : ks;
+    for (int j0 = 0; j0 < nit; j0 += kMerge) {
+        float tx = 0.f, ty = 0.f, tz = 0.f;
+        const int lim = min(j0 + kMerge, nit);
+        for (int jj = j0; jj < lim; jj += kU) {
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const float4 pj = src[(jj + u) * st];
+                const float dx = pj.x - xi.x;
+                const float dy = pj.y - xi.y;
+                const float dz = pj.z - xi.z;
+                float sp = __builtin_fmaf(dx, dx, c.eps);
+                sp = __builtin_fmaf(dy, dy, sp);
+                sp = __builtin_fmaf(dz, dz, sp);
+                const float y = __builtin_amdgcn_rsqf(sp);
+                const float t = __builtin_fmaf(sp, c.alpha, c.beta);
+                float p = __builtin_fmaf(c.b5, t, c.b4);
+                p = __builtin_fmaf(p, t, c.b3);
+                p = __builtin_fmaf(p, t, c.b2);
+                p = __builtin_fmaf(p, t, c.b1);
+                p = __builtin_fmaf(p, t, c.b0);
+                const float y2 = y * y;
+                const float f = __builtin_fmaf(y2, y, -p);
+                const float mf = sp < c.rc2e ? (UNI ? f : pj.w * f) : 0.0f;
+                tx = __builtin_fmaf(mf, dx, tx);
+                ty = __builtin_fmaf(mf, dy, ty);
+                tz = __builtin_fmaf(mf, dz, tz);
+            }
+        }
+        if (UNI) {
+            tx *= mref;
+            ty *= mref;
+            tz *= mref;
+        }
+        kahan_add(s[0], cc[0], tx);
+        kahan_add(s[1], cc[1], ty);
+        kahan_add(s[2], cc[2], tz);
+    }
+}
+
+__global__ __launch_bounds__(kWave, HSR_MIN_WAVES) void k_pair_force(
     const WorkItem* __restrict__ items, const int* __restrict__ n_items_dev,
     const float4* __restrict__ rec, const int* __restrict__ cs,
     const int* __restrict__ perm, Geom g, PairParams P,
@@ -276,60 +387,41 @@ __global__ __launch_bounds__(kWave) void k_pair_force(
     const float4 xi = L.ki >= 0 ? rec[L.ki] : make_float4(0.f, 0.f, 0.f, 0.f);
     float4 lo, hi;
     target_box(xi, L.ki >= 0, &lo, &hi);
+    const float mref = uniform(__shfl(xi.w, 0));
+    const bool targets_equal = __ballot(L.ki >= 0 && xi.w != mref) == 0ull;
+    const float4 pad = pad_source(lo, Lc);
     __syncthreads();
 
-    const float eps = P.eps, rc2e = P.rc2e, alpha = P.alpha, beta = P.beta;
-    const float b0 = P.b[0], b1 = P.b[1], b2 = P.b[2], b3 = P.b[3], b4 = P.b[4],
-                b5 = P.b[5];
-    float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
+    const ForceConsts c = force_consts(P);
+    float s[3] = {0.f, 0.f, 0.f}, cc[3] = {0.f, 0.f, 0.f};
 
-    Round<false> R;
-    load_round(sg, 0, total, rec, rec, R);
+    Round<false, kT> R;
+    if (HSR_PREFETCH) load_round(sg, 0, total, rec, rec, R);
     for (int cursor = 0; cursor < total; cursor += kT) {
-        const int cnt = compact_round(R, lo, hi, P.cull2, Lc, tile, tile, nullptr);
+        bool mixed;
+        if (!HSR_PREFETCH) load_round(sg, cursor, total, rec, rec, R);
+        const int cnt = compact_round(R, lo, hi, P.cull2, Lc, mref, tile, tile,
+                                      nullptr, &mixed);
         const int cntp = padded_count(cnt, L.ks);
-        for (int q = cnt + lane; q < cntp; q += kWave) tile[q] = pad_source(Lc);
+        for (int q = cnt + lane; q < cntp; q += kWave) tile[q] = pad;
         __syncthreads();
-        if (cursor + kT < total) load_round(sg, cursor + kT, total, rec, rec, R);
+        if (HSR_PREFETCH && cursor + kT < total)
+            load_round(sg, cursor + kT, total, rec, rec, R);
         const int nit = cntp / L.ks;          // sources per lane in this tile
         const float4* src = tile + L.r;
-        for (int j0 = 0; j0 < nit; j0 += kMerge) {
-            float tx = 0.f, ty = 0.f, tz = 0.f;
-            const int lim = min(j0 + kMerge, nit);
-            for (int jj = j0; jj < lim; jj += kU) {
-#pragma unroll
-                for (int u = 0; u < kU; ++u) {
-                    const float4 pj = src[(jj + u) * L.ks];
-                    const float dx = pj.x - xi.x;
-                    const float dy = pj.y - xi.y;
-                    const float dz = pj.z - xi.z;
-                    float sp = __builtin_fmaf(dx, dx, eps);
-                    sp = __builtin_fmaf(dy, dy, sp);
-                    sp = __builtin_fmaf(dz, dz, sp);
-                    const float y = __builtin_amdgcn_rsqf(sp);
-                    const float t = __builtin_fmaf(sp, alpha, beta);
-                    float p = __builtin_fmaf(b5, t, b4);
-                    p = __builtin_fmaf(p, t, b3);
-                    p = __builtin_fmaf(p, t, b2);
-                    p = __builtin_fmaf(p, t, b1);
-                    p = __builtin_fmaf(p, t, b0);
-                    const float y2 = y * y;
-                    const float f = __builtin_fmaf(y2, y, -p);
-                    const float mf = sp < rc2e ? pj.w * f : 0.0f;
-                    tx = __builtin_fmaf(mf, dx, tx);
-                    ty = __builtin_fmaf(mf, dy, ty);
-                    tz = __builtin_fmaf(mf, dz, tz);
-                }
-            }
-            kahan_add(sx, cx, tx);
-            kahan_add(sy, cy, ty);
-            kahan_add(sz, cz, tz);
+        const bool uni = targets_equal && !mixed;
+        if (L.ks == 1) {
+            if (uni) force_tile<1, true>(src, 1, nit, xi, c, mref, s, cc);
+            else force_tile<1, false>(src, 1, nit, xi, c, mref, s, cc);
+        } else {
+            if (uni) force_tile<0, true>(src, L.ks, nit, xi, c, mref, s, cc);
+            else force_tile<0, false>(src, L.ks, nit, xi, c, mref, s, cc);
         }
         __syncthreads();
     }
-    const double ax = group_sum((double)sx - (double)cx, L.ks);
-    const double ay = group_sum((double)sy - (double)cy, L.ks);
-    const double az = group_sum((double)sz - (double)cz, L.ks);
+    const double ax = group_sum((double)s[0] - (double)cc[0], L.ks);
+    const double ay = group_sum((double)s[1] - (double)cc[1], L.ks);
+    const double az = group_sum((double)s[2] - (double)cc[2], L.ks);
     if (L.ki >= 0 && L.r == 0) {
         const int64_t o = 3 * (int64_t)perm[L.ki];
         out_acc[o] = (float)ax;
@@ -360,10 +452,12 @@ __global__ __launch_bounds__(kWave) void k_pair_count(
     __syncthreads();
     unsigned long long inside = 0;
     int kept = 0;
-    Round<false> R;
+    Round<false, kT> R;
     for (int cursor = 0; cursor < total; cursor += kT) {
         load_round(sg, cursor, total, rec, rec, R);
-        const int cnt = compact_round(R, lo, hi, P.cull2, Lc, tile, tile, tidx);
+        bool mixed;
+        const int cnt = compact_round(R, lo, hi, P.cull2, Lc, 0.0f, tile, tile, tidx,
+                                      &mixed);
         kept += cnt;
         __syncthreads();
         for (int j = L.r; j < cnt; j += L.ks) {
@@ -392,16 +486,98 @@ __global__ __launch_bounds__(kWave) void k_pair_count(
 
 // ------------------------------------------------------------ adjoint
 
+struct VjpConsts {
+    ForceConsts f;
+    float q0, q1, q2, q3, q4;
+};
+
+// Same tile walk as force_tile for the VJP pair term
+//   f w + 2 f'(s) (d.w) d,   w = m_k g_j - m_j g_k.
+// UNI: all masses equal mref, so w = mref (g_j - g_k) and mref multiplies
+// the partial sums.
+template <int KS, bool UNI>
+__device__ __forceinline__ void vjp_tile(const float4* __restrict__ srcA,
+                                         const float4* __restrict__ srcB,
+                                         int ks, int nit, float4 xk, float4 gk,
+                                         const VjpConsts& v, float mref,
+                                         float* s, float* cc) {
+    const int st = KS > 0 ? KS : ks;
+    const ForceConsts& c = v.f;
+    const float mk = xk.w;
+    for (int j0 = 0; j0 < nit; j0 += kMerge) {
+        float tx = 0.f, ty = 0.f, tz = 0.f;
+        const int lim = min(j0 + kMerge, nit);
+        for (int jj = j0; jj < lim; jj += kVU) {
+#pragma unroll
+            for (int u = 0; u < kVU; ++u) {
+                const float4 pj = srcA[(jj + u) * st];
+                const float4 gj = srcB[(jj + u) * st];
+                const float dx = pj.x - xk.x;
+                const float dy = pj.y - xk.y;
+                const float dz = pj.z - xk.z;
+                float sp = __builtin_fmaf(dx, dx, c.eps);
+                sp = __builtin_fmaf(dy, dy, sp);
+                sp = __builtin_fmaf(dz, dz, sp);
+                const float y = __builtin_amdgcn_rsqf(sp);
+                const float t = __builtin_fmaf(sp, c.alpha, c.beta);
+                float p = __builtin_fmaf(c.b5, t, c.b4);
+                p = __builtin_fmaf(p, t, c.b3);
+                p = __builtin_fmaf(p, t, c.b2);
+                p = __builtin_fmaf(p, t, c.b1);
+                p = __builtin_fmaf(p, t, c.b0);
+                float q = __builtin_fmaf(v.q4, t, v.q3);
+                q = __builtin_fmaf(q, t, v.q2);
+                q = __builtin_fmaf(q, t, v.q1);
+                q = __builtin_fmaf(q, t, v.q0);
+                const float y2 = y * y;
+                const float y3 = y2 * y;
+                const float y5 = y3 * y2;
+                const bool in = sp < c.rc2e;
+                const float f = in ? y3 - p : 0.0f;
+                const float f2 = in ? __builtin_fmaf(-3.0f, y5, -q) : 0.0f;
+                float wx, wy, wz;
+                if (UNI) {
+                    wx = gj.x - gk.x;
+                    wy = gj.y - gk.y;
+                    wz = gj.z - gk.z;
+                } else {
+                    wx = __builtin_fmaf(mk, gj.x, -(pj.w * gk.x));
+                    wy = __builtin_fmaf(mk, gj.y, -(pj.w * gk.y));
+                    wz = __builtin_fmaf(mk, gj.z, -(pj.w * gk.z));
+                }
+                float dw = dx * wx;
+                dw = __builtin_fmaf(dy, wy, dw);
+                dw = __builtin_fmaf(dz, wz, dw);
+                const float cd = f2 * dw;
+                tx = __builtin_fmaf(f, wx, tx);
+                ty = __builtin_fmaf(f, wy, ty);
+                tz = __builtin_fmaf(f, wz, tz);
+                tx = __builtin_fmaf(cd, dx, tx);
+                ty = __builtin_fmaf(cd, dy, ty);
+                tz = __builtin_fmaf(cd, dz, tz);
+            }
+        }
+        if (UNI) {
+            tx *= mref;
+            ty *= mref;
+            tz *= mref;
+        }
+        kahan_add(s[0], cc[0], tx);
+        kahan_add(s[1], cc[1], ty);
+        kahan_add(s[2], cc[2], tz);
+    }
+}
+
 // dL/dx_k = sum_j [f w + 2 f'(s) (d.w) d],  w = m_k g_j - m_j g_k,
 // the transpose of the Jacobian of the pair term applied to the cotangents.
-__global__ __launch_bounds__(kWave) void k_pair_vjp(
+__global__ __launch_bounds__(kWave, HSR_VJP_MIN_WAVES) void k_pair_vjp(
     const WorkItem* __restrict__ items, const int* __restrict__ n_items_dev,
     const float4* __restrict__ rec, const float4* __restrict__ gsorted,
     const int* __restrict__ cs, const int* __restrict__ perm, Geom g,
     PairParams P, double* __restrict__ out_grad) {
     __shared__ Segments sg;
-    __shared__ float4 tileA[kT];
-    __shared__ float4 tileB[kT];
+    __shared__ float4 tileA[kVT];
+    __shared__ float4 tileB[kVT];
     if ((int)blockIdx.x >= *n_items_dev) return;
     const WorkItem it = items[blockIdx.x];
     const int lane = threadIdx.x;
@@ -412,85 +588,46 @@ __global__ __launch_bounds__(kWave) void k_pair_vjp(
     const float4 gk = L.ki >= 0 ? gsorted[L.ki] : make_float4(0.f, 0.f, 0.f, 0.f);
     float4 lo, hi;
     target_box(xk, L.ki >= 0, &lo, &hi);
+    const float mref = uniform(__shfl(xk.w, 0));
+    const bool targets_equal = __ballot(L.ki >= 0 && xk.w != mref) == 0ull;
+    const float4 pad = pad_source(lo, Lc);
     __syncthreads();
 
-    const float eps = P.eps, rc2e = P.rc2e, alpha = P.alpha, beta = P.beta;
-    const float b0 = P.b[0], b1 = P.b[1], b2 = P.b[2], b3 = P.b[3], b4 = P.b[4],
-                b5 = P.b[5];
-    const float q0 = P.db2[0], q1 = P.db2[1], q2 = P.db2[2], q3 = P.db2[3],
-                q4 = P.db2[4];
-    const float mk = xk.w;
-    float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
+    const VjpConsts v{force_consts(P), P.db2[0], P.db2[1], P.db2[2], P.db2[3],
+                      P.db2[4]};
+    float s[3] = {0.f, 0.f, 0.f}, cc[3] = {0.f, 0.f, 0.f};
 
-    Round<true> R;
-    load_round(sg, 0, total, rec, gsorted, R);
-    for (int cursor = 0; cursor < total; cursor += kT) {
-        const int cnt = compact_round(R, lo, hi, P.cull2, Lc, tileA, tileB, nullptr);
-        const int cntp = padded_count(cnt, L.ks);
+    Round<true, kVT> R;
+    if (HSR_VJP_PREFETCH) load_round(sg, 0, total, rec, gsorted, R);
+    for (int cursor = 0; cursor < total; cursor += kVT) {
+        bool mixed;
+        if (!HSR_VJP_PREFETCH) load_round(sg, cursor, total, rec, gsorted, R);
+        const int cnt = compact_round(R, lo, hi, P.cull2, Lc, mref, tileA, tileB,
+                                      nullptr, &mixed);
+        const int cntp = padded_count(cnt, L.ks, kVU);
         for (int q = cnt + lane; q < cntp; q += kWave) {
-            tileA[q] = pad_source(Lc);
+            tileA[q] = pad;
             tileB[q] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
         __syncthreads();
-        if (cursor + kT < total) load_round(sg, cursor + kT, total, rec, gsorted, R);
+        if (HSR_VJP_PREFETCH && cursor + kVT < total)
+            load_round(sg, cursor + kVT, total, rec, gsorted, R);
         const int nit = cntp / L.ks;
         const float4* srcA = tileA + L.r;
         const float4* srcB = tileB + L.r;
-        for (int j0 = 0; j0 < nit; j0 += kMerge) {
-            float tx = 0.f, ty = 0.f, tz = 0.f;
-            const int lim = min(j0 + kMerge, nit);
-            for (int jj = j0; jj < lim; jj += kU) {
-#pragma unroll
-                for (int u = 0; u < kU; ++u) {
-                    const float4 pj = srcA[(jj + u) * L.ks];
-                    const float4 gj = srcB[(jj + u) * L.ks];
-                    const float dx = pj.x - xk.x;
-                    const float dy = pj.y - xk.y;
-                    const float dz = pj.z - xk.z;
-                    float sp = __builtin_fmaf(dx, dx, eps);
-                    sp = __builtin_fmaf(dy, dy, sp);
-                    sp = __builtin_fmaf(dz, dz, sp);
-                    const float y = __builtin_amdgcn_rsqf(sp);
-                    const float t = __builtin_fmaf(sp, alpha, beta);
-                    float p = __builtin_fmaf(b5, t, b4);
-                    p = __builtin_fmaf(p, t, b3);
-                    p = __builtin_fmaf(p, t, b2);
-                    p = __builtin_fmaf(p, t, b1);
-                    p = __builtin_fmaf(p, t, b0);
-                    float q = __builtin_fmaf(q4, t, q3);
-                    q = __builtin_fmaf(q, t, q2);
-                    q = __builtin_fmaf(q, t, q1);
-                    q = __builtin_fmaf(q, t, q0);
-                    const float y2 = y * y;
-                    const float y3 = y2 * y;
-                    const float y5 = y3 * y2;
-                    const bool in = sp < rc2e;
-                    const float f = in ? y3 - p : 0.0f;
-                    const float f2 = in ? __builtin_fmaf(-3.0f, y5, -q) : 0.0f;
-                    const float wx = __builtin_fmaf(mk, gj.x, -(pj.w * gk.x));
-                    const float wy = __builtin_fmaf(mk, gj.y, -(pj.w * gk.y));
-                    const float wz = __builtin_fmaf(mk, gj.z, -(pj.w * gk.z));
-                    float dw = dx * wx;
-                    dw = __builtin_fmaf(dy, wy, dw);
-                    dw = __builtin_fmaf(dz, wz, dw);
-                    const float c = f2 * dw;
-                    tx = __builtin_fmaf(f, wx, tx);
-                    ty = __builtin_fmaf(f, wy, ty);
-                    tz = __builtin_fmaf(f, wz, tz);
-                    tx = __builtin_fmaf(c, dx, tx);
-                    ty = __builtin_fmaf(c, dy, ty);
-                    tz = __builtin_fmaf(c, dz, tz);
-                }
-            }
-            kahan_add(sx, cx, tx);
-            kahan_add(sy, cy, ty);
-            kahan_add(sz, cz, tz);
+        const bool uni = targets_equal && !mixed;
+        if (L.ks == 1) {
+            if (uni) vjp_tile<1, true>(srcA, srcB, 1, nit, xk, gk, v, mref, s, cc);
+            else vjp_tile<1, false>(srcA, srcB, 1, nit, xk, gk, v, mref, s, cc);
+        } else {
+            if (uni) vjp_tile<0, true>(srcA, srcB, L.ks, nit, xk, gk, v, mref, s, cc);
+            else vjp_tile<0, false>(srcA, srcB, L.ks, nit, xk, gk, v, mref, s, cc);
         }
         __syncthreads();
     }
-    const double gx = group_sum((double)sx - (double)cx, L.ks);
-    const double gy = group_sum((double)sy - (double)cy, L.ks);
-    const double gz = group_sum((double)sz - (double)cz, L.ks);
+    const double gx = group_sum((double)s[0] - (double)cc[0], L.ks);
+    const double gy = group_sum((double)s[1] - (double)cc[1], L.ks);
+    const double gz = group_sum((double)s[2] - (double)cc[2], L.ks);
     if (L.ki >= 0 && L.r == 0) {
         const int64_t o = 3 * (int64_t)perm[L.ki];
         out_grad[o] = gx;
