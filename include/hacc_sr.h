@@ -87,8 +87,11 @@ int hacc_sr_set_workspace(void *dev_ptr, size_t bytes);
  * P^3M code, Sec. II).  Outputs, all caller-owned device arrays:
  *   cell_start (N^3 + 1) int32: particles of cell c are sorted entries
  *       [cell_start[c], cell_start[c+1]); cell index c = (cx * N + cy) * N + cz.
- *   perm (n) int32: sorted entry k holds input particle perm[k]; within a
- *       cell, input order is kept (a stable counting sort).
+ *   perm (n) int32: sorted entry k holds input particle perm[k].  Within a
+ *       cell, particles are ordered by the Morton code of their sub-cell
+ *       (the cell split into S^3 equal sub-cells, S = 4 when the cell index
+ *       and the code fit in 31 bits, else 2 or 1) and then by input index,
+ *       so the order is deterministic.
  *   sorted_rec (n, 4) float32: (x - x_c, y - y_c, z - z_c, m) per sorted
  *       entry, the position relative to its cell's lower corner, rounded
  *       from float64 to float32.

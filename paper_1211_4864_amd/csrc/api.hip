@@ -133,6 +133,8 @@ struct Layout {
     int64_t ncell;
     int max_items;
     int radix_nb;
+    int digit_bits;   // radix digit width (8..11)
+    int passes;       // radix passes over the sort key
 };
 
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -144,7 +146,12 @@ Layout layout_for(int64_t n, const Geom& g) {
     // a cell of c targets gives floor(c / 64) full items and at most two more
     L.max_items = (int)(2 * std::min<int64_t>(n, L.ncell) + n / kItemI + 1);
     L.radix_nb = radix_blocks(nn > 0 ? nn : 1);
-    const int64_t scan_n = std::max<int64_t>((int64_t)256 * L.radix_nb, L.ncell + 1);
+    // at most three stable passes: digits of ceil(bits / 3) bits, 8 to 11
+    const int bits = key_bits(L.ncell) + g.sbits;
+    L.digit_bits = std::min(kMaxDigitBits, std::max(8, (bits + 2) / 3));
+    L.passes = (bits + L.digit_bits - 1) / L.digit_bits;
+    const int64_t hist_n = ((int64_t)1 << L.digit_bits) * L.radix_nb;
+    const int64_t scan_n = std::max<int64_t>(hist_n, L.ncell + 1);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t at = off;
@@ -157,9 +164,11 @@ Layout layout_for(int64_t n, const Geom& g) {
     L.keys_b = take(ni);
     L.vals_b = take(ni);
     L.counts = take(sizeof(int) * (size_t)(L.ncell + 1));
-    L.hist = take(sizeof(int) * (size_t)256 * L.radix_nb);
+    L.hist = take(sizeof(int) * (size_t)hist_n);
     L.scan_tmp = take(sizeof(int) * scan_tmp_ints((int)scan_n));
     L.rec = take(sizeof(float4) * (size_t)std::max<int64_t>(n, 1));
+    // also holds the records in input order during binning (the sorted
+    // cotangents are gathered only after the records)
     L.gsorted = take(sizeof(float4) * (size_t)std::max<int64_t>(n, 1));
     L.cell_items = take(sizeof(int) * (size_t)(L.ncell + 1));
     L.items = take(sizeof(WorkItem) * (size_t)L.max_items);
@@ -194,17 +203,19 @@ int bin_impl(const double* pos, const float* mass, int64_t n, const Geom& g,
     int* vb = ws_at<int>(L.vals_b);
     int* hist = ws_at<int>(L.hist);
     int* tmp = ws_at<int>(L.scan_tmp);
+    float4* rec_in = ws_at<float4>(L.gsorted);
     const int ncp = (int)(L.ncell + 1);
-    HIP_TRY(launch_fill_i32(cell_start, ncp, 0, g_stream));
-    HIP_TRY(launch_cell_keys(pos, nn, g, ka, va, cell_start, g_stream));
-    HIP_TRY(launch_scan_exclusive(cell_start, cell_start, ncp, tmp, g_stream));
-    const int passes = (key_bits(L.ncell) + g.sbits + 7) / 8;
-    for (int p = 0; p < passes; ++p) {
-        HIP_TRY(launch_radix_pass(ka, va, kb, vb, nn, 8 * p, hist, tmp, g_stream));
+    HIP_TRY(launch_cell_keys(pos, mass, nn, g, ka, va, rec_in, g_stream));
+    for (int p = 0; p < L.passes; ++p) {
+        HIP_TRY(launch_radix_pass(ka, va, kb, vb, nn, L.digit_bits * p,
+                                  L.digit_bits, hist, tmp, g_stream));
         std::swap(ka, kb);
         std::swap(va, vb);
     }
-    HIP_TRY(launch_gather_records(pos, mass, ka, va, nn, g, rec, g_stream));
+    HIP_TRY(launch_fill_i32(cell_start, ncp, 0, g_stream));
+    HIP_TRY(launch_cell_hist(ka, nn, g.sbits, cell_start, g_stream));
+    HIP_TRY(launch_scan_exclusive(cell_start, cell_start, ncp, tmp, g_stream));
+    HIP_TRY(launch_gather_records(rec_in, va, nn, rec, g_stream));
     if (perm_user) {
         HIP_TRY(hipMemcpyAsync(perm_user, va, sizeof(int) * (size_t)nn,
                                hipMemcpyDeviceToDevice, g_stream));

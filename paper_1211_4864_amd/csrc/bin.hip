@@ -1,6 +1,7 @@
-// Chaining-mesh binning: cell keys and occupancy histogram, exclusive prefix
-// scan, stable LSD radix scatter, and the gather of cell-relative float32
-// records.  The sort key is the cell index followed by the Morton code of the
+// Chaining-mesh binning: cell keys and cell-relative float32 records,
+// stable LSD radix passes, the occupancy histogram of the sorted keys (wave-
+// aggregated atomics: sorted keys arrive in runs), its exclusive prefix scan
+// (cell_start), and the gather of the records into sorted order.  The sort key is the cell index followed by the Morton code of the
 // particle's sub-cell (4^3 per cell when the key has room), so a cell's
 // particles are grouped spatially and, within a sub-cell, keep their input
 // order: the binning is deterministic.
@@ -25,11 +26,12 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
     return l == 0 ? 0ull : (~0ull >> (64 - l));
 }
 
-// Lanes of the wave holding the same 8-bit value (a match over 8 ballots).
-__device__ __forceinline__ uint64_t peers8(unsigned v, bool active) {
+// Lanes of the wave holding the same BITS-bit value (a match over ballots).
+template <int BITS>
+__device__ __forceinline__ uint64_t peers(unsigned v, bool active) {
     uint64_t m = __ballot(active);
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
+    for (int b = 0; b < BITS; ++b) {
         const bool bit = (v >> b) & 1u;
         const uint64_t bl = __ballot(bit && active);
         m &= bit ? bl : ~bl;
@@ -63,43 +65,56 @@ __device__ __forceinline__ int axis_sub(double xw, int c, const Geom& g, int S) 
     return (int)t;
 }
 
+// Sort key (cell index, then the sub-cell Morton code) and the float32
+// record (position relative to the cell's lower corner, mass) of every
+// particle, in input order.
 __global__ __launch_bounds__(kBlock) void k_cell_keys(
-    const double* __restrict__ pos, int n, Geom g, int* __restrict__ keys,
-    int* __restrict__ vals, int* __restrict__ counts) {
+    const double* __restrict__ pos, const float* __restrict__ mass, int n,
+    Geom g, int* __restrict__ keys, int* __restrict__ vals,
+    float4* __restrict__ rec) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
-    const bool active = i < n;
-    int key = 0;
-    if (active) {
-        double xw, yw, zw;
-        const int cx = axis_cell(pos[3 * (int64_t)i], g, &xw);
-        const int cy = axis_cell(pos[3 * (int64_t)i + 1], g, &yw);
-        const int cz = axis_cell(pos[3 * (int64_t)i + 2], g, &zw);
-        key = (cx * g.N + cy) * g.N + cz;
-        int code = 0;
-        const int levels = g.sbits / 3;
-        if (levels > 0) {
-            const int S = 1 << levels;
-            const int sx = axis_sub(xw, cx, g, S);
-            const int sy = axis_sub(yw, cy, g, S);
-            const int sz = axis_sub(zw, cz, g, S);
-            for (int b = 0; b < levels; ++b)
-                code |= (((sx >> b) & 1) << (3 * b + 2)) |
-                        (((sy >> b) & 1) << (3 * b + 1)) | (((sz >> b) & 1) << (3 * b));
-        }
-        keys[i] = (key << g.sbits) | code;
-        vals[i] = i;
+    if (i >= n) return;
+    double xw, yw, zw;
+    const int cx = axis_cell(pos[3 * (int64_t)i], g, &xw);
+    const int cy = axis_cell(pos[3 * (int64_t)i + 1], g, &yw);
+    const int cz = axis_cell(pos[3 * (int64_t)i + 2], g, &zw);
+    const int key = (cx * g.N + cy) * g.N + cz;
+    int code = 0;
+    const int levels = g.sbits / 3;
+    if (levels > 0) {
+        const int S = 1 << levels;
+        const int sx = axis_sub(xw, cx, g, S);
+        const int sy = axis_sub(yw, cy, g, S);
+        const int sz = axis_sub(zw, cz, g, S);
+        for (int b = 0; b < levels; ++b)
+            code |= (((sx >> b) & 1) << (3 * b + 2)) |
+                    (((sy >> b) & 1) << (3 * b + 1)) | (((sz >> b) & 1) << (3 * b));
     }
-    // Histogram with the first lane's cell aggregated over the wave: inputs
-    // that arrive spatially ordered then cost one atomic per run.
-    const int lead = __shfl(key, __ffsll((unsigned long long)__ballot(active)) - 1);
-    const uint64_t same = __ballot(active && key == lead);
-    if (active) {
-        if (key == lead) {
-            if ((uint64_t)(same & lanemask_lt()) == 0ull)
-                atomicAdd(&counts[key], __popcll(same));
-        } else {
-            atomicAdd(&counts[key], 1);
-        }
+    keys[i] = (key << g.sbits) | code;
+    vals[i] = i;
+    float4 r;
+    r.x = (float)(xw - (double)cx * g.Lc);
+    r.y = (float)(yw - (double)cy * g.Lc);
+    r.z = (float)(zw - (double)cz * g.Lc);
+    r.w = mass ? mass[i] : 0.0f;
+    rec[i] = r;
+}
+
+// Occupancy of every cell from the sorted keys.  Consecutive entries share
+// cells, so each wave adds one count per distinct cell it holds.
+__global__ __launch_bounds__(kBlock) void k_cell_hist(
+    const int* __restrict__ keys, int n, int sbits, int* __restrict__ counts) {
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    bool pending = k < n;
+    const int cell = pending ? keys[k] >> sbits : 0;
+    uint64_t left = __ballot(pending);
+    while (left) {
+        const int lead = __shfl(cell, __ffsll((unsigned long long)left) - 1);
+        const uint64_t same = __ballot(pending && cell == lead);
+        if (pending && cell == lead && (same & lanemask_lt()) == 0ull)
+            atomicAdd(&counts[cell], __popcll(same));
+        if (cell == lead) pending = false;
+        left &= ~same;
     }
 }
 
@@ -194,60 +209,67 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(
 }
 
 // ---------------------------------------------------------------- radix
-// One stable counting-sort pass on an 8-bit digit of the cell key.
+// One stable counting-sort pass on a DB-bit digit of the sort key.
 
+template <int DB>
 __global__ __launch_bounds__(kBlock) void k_radix_hist(
     const int* __restrict__ keys, int n, int shift, int* __restrict__ hist,
     int nblocks) {
-    __shared__ int h[256];
-    h[threadIdx.x] = 0;
+    constexpr int R = 1 << DB;
+    __shared__ int h[R];
+    for (int q = threadIdx.x; q < R; q += kBlock) h[q] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kTile;
 #pragma unroll 4
     for (int it = 0; it < kItems; ++it) {
         const int64_t e = base + it * kBlock + threadIdx.x;
         const bool active = e < n;
-        const unsigned d = active ? ((unsigned)keys[e] >> shift) & 255u : 0u;
-        const uint64_t pm = peers8(d, active);
+        const unsigned d = active ? ((unsigned)keys[e] >> shift) & (unsigned)(R - 1) : 0u;
+        const uint64_t pm = peers<DB>(d, active);
         if (active && (pm & lanemask_lt()) == 0ull) atomicAdd(&h[d], __popcll(pm));
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+    for (int q = threadIdx.x; q < R; q += kBlock)
+        hist[(int64_t)q * nblocks + blockIdx.x] = h[q];
 }
 
+template <int DB>
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(
     const int* __restrict__ kin, const int* __restrict__ vin,
     int* __restrict__ kout, int* __restrict__ vout, int n, int shift,
     const int* __restrict__ offs, int nblocks) {
+    constexpr int R = 1 << DB;
     constexpr int kW = kBlock / kWave;
-    __shared__ int base_d[256];     // global offset of this block's digit d
-    __shared__ int run_d[256];      // digit d entries already placed by this block
-    __shared__ int wcnt[kW][256];
-    base_d[threadIdx.x] = offs[(int64_t)threadIdx.x * nblocks + blockIdx.x];
-    run_d[threadIdx.x] = 0;
+    __shared__ int base_d[R];     // global offset of this block's digit d
+    __shared__ int run_d[R];      // digit d entries already placed by this block
+    __shared__ int wcnt[kW][R];
+    for (int q = threadIdx.x; q < R; q += kBlock) {
+        base_d[q] = offs[(int64_t)q * nblocks + blockIdx.x];
+        run_d[q] = 0;
+    }
     const int w = threadIdx.x / kWave;
     const int64_t base = (int64_t)blockIdx.x * kTile;
     for (int it = 0; it < kItems; ++it) {
+        for (int q = threadIdx.x; q < R; q += kBlock)
 #pragma unroll
-        for (int q = 0; q < kW; ++q) wcnt[q][threadIdx.x] = 0;
+            for (int v = 0; v < kW; ++v) wcnt[v][q] = 0;
         __syncthreads();
         const int64_t e = base + it * kBlock + threadIdx.x;
         const bool active = e < n;
         const int key = active ? kin[e] : 0;
         const int val = active ? vin[e] : 0;
-        const unsigned d = ((unsigned)key >> shift) & 255u;
-        const uint64_t pm = peers8(d, active);
+        const unsigned d = ((unsigned)key >> shift) & (unsigned)(R - 1);
+        const uint64_t pm = peers<DB>(d, active);
         const int rank = __popcll(pm & lanemask_lt());
         if (active && rank == 0) wcnt[w][d] = __popcll(pm);
         __syncthreads();
-        // digit t: exclusive prefix over the waves of this round
-        {
-            const int t = threadIdx.x;
+        // each digit: exclusive prefix over the waves of this round
+        for (int t = threadIdx.x; t < R; t += kBlock) {
             int acc = run_d[t];
 #pragma unroll
-            for (int q = 0; q < kW; ++q) {
-                const int c = wcnt[q][t];
-                wcnt[q][t] = acc;
+            for (int v = 0; v < kW; ++v) {
+                const int c = wcnt[v][t];
+                wcnt[v][t] = acc;
                 acc += c;
             }
             run_d[t] = acc;
@@ -263,26 +285,11 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(
 }
 
 __global__ __launch_bounds__(kBlock) void k_gather_records(
-    const double* __restrict__ pos, const float* __restrict__ mass,
-    const int* __restrict__ keys, const int* __restrict__ perm, int n, Geom g,
+    const float4* __restrict__ rec_in, const int* __restrict__ perm, int n,
     float4* __restrict__ rec) {
     const int k = blockIdx.x * kBlock + threadIdx.x;
     if (k >= n) return;
-    const int i = perm[k];
-    const int key = keys[k] >> g.sbits;
-    const int cz = key % g.N;
-    const int cy = (key / g.N) % g.N;
-    const int cx = key / (g.N * g.N);
-    double xw, yw, zw;
-    axis_cell(pos[3 * (int64_t)i], g, &xw);
-    axis_cell(pos[3 * (int64_t)i + 1], g, &yw);
-    axis_cell(pos[3 * (int64_t)i + 2], g, &zw);
-    float4 r;
-    r.x = (float)(xw - (double)cx * g.Lc);
-    r.y = (float)(yw - (double)cy * g.Lc);
-    r.z = (float)(zw - (double)cz * g.Lc);
-    r.w = mass ? mass[i] : 0.0f;
-    rec[k] = r;
+    rec[k] = rec_in[perm[k]];
 }
 
 __global__ __launch_bounds__(kBlock) void k_gather_vec3(
@@ -303,11 +310,20 @@ inline int blocks_for(int64_t n, int per) { return (int)((n + per - 1) / per); }
 
 }  // namespace
 
-hipError_t launch_cell_keys(const double* pos, int n, Geom g, int* keys,
-                            int* vals, int* counts, hipStream_t st) {
+hipError_t launch_cell_keys(const double* pos, const float* mass, int n,
+                            Geom g, int* keys, int* vals, float4* rec,
+                            hipStream_t st) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_cell_keys, dim3(blocks_for(n, kBlock)), dim3(kBlock),
-                       0, st, pos, n, g, keys, vals, counts);
+                       0, st, pos, mass, n, g, keys, vals, rec);
+    return hipGetLastError();
+}
+
+hipError_t launch_cell_hist(const int* keys_sorted, int n, int sbits,
+                            int* counts, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cell_hist, dim3(blocks_for(n, kBlock)), dim3(kBlock),
+                       0, st, keys_sorted, n, sbits, counts);
     return hipGetLastError();
 }
 
@@ -326,27 +342,40 @@ hipError_t launch_scan_exclusive(const int* in, int* out, int n, int* tmp,
 
 int radix_blocks(int n) { return blocks_for(n, kTile); }
 
-hipError_t launch_radix_pass(const int* kin, const int* vin, int* kout,
-                             int* vout, int n, int shift, int* hist,
-                             int* scan_tmp, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
+namespace {
+template <int DB>
+hipError_t radix_pass(const int* kin, const int* vin, int* kout, int* vout,
+                      int n, int shift, int* hist, int* scan_tmp,
+                      hipStream_t st) {
     const int nb = radix_blocks(n);
-    hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kBlock), 0, st, kin, n,
+    hipLaunchKernelGGL(k_radix_hist<DB>, dim3(nb), dim3(kBlock), 0, st, kin, n,
                        shift, hist, nb);
-    hipError_t e = launch_scan_exclusive(hist, hist, 256 * nb, scan_tmp, st);
+    hipError_t e = launch_scan_exclusive(hist, hist, (1 << DB) * nb, scan_tmp, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kBlock), 0, st, kin,
+    hipLaunchKernelGGL(k_radix_scatter<DB>, dim3(nb), dim3(kBlock), 0, st, kin,
                        vin, kout, vout, n, shift, (const int*)hist, nb);
     return hipGetLastError();
 }
+}  // namespace
 
-hipError_t launch_gather_records(const double* pos, const float* mass,
-                                 const int* keys_sorted, const int* perm,
-                                 int n, Geom g, float4* rec, hipStream_t st) {
+hipError_t launch_radix_pass(const int* kin, const int* vin, int* kout,
+                             int* vout, int n, int shift, int digit_bits,
+                             int* hist, int* scan_tmp, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    switch (digit_bits) {
+        case 8: return radix_pass<8>(kin, vin, kout, vout, n, shift, hist, scan_tmp, st);
+        case 9: return radix_pass<9>(kin, vin, kout, vout, n, shift, hist, scan_tmp, st);
+        case 10: return radix_pass<10>(kin, vin, kout, vout, n, shift, hist, scan_tmp, st);
+        case 11: return radix_pass<11>(kin, vin, kout, vout, n, shift, hist, scan_tmp, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_gather_records(const float4* rec_in, const int* perm, int n,
+                                 float4* rec, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_gather_records, dim3(blocks_for(n, kBlock)),
-                       dim3(kBlock), 0, st, pos, mass, keys_sorted, perm, n, g,
-                       rec);
+                       dim3(kBlock), 0, st, rec_in, perm, n, rec);
     return hipGetLastError();
 }
 

@@ -47,18 +47,21 @@ constexpr int kItemI = 64;     // lanes of a wave
 // ---- launch wrappers (each defined in the translation unit of its kernels)
 
 // binning (bin.hip)
-hipError_t launch_cell_keys(const double* pos, int n, Geom g, int* keys,
-                            int* vals, int* counts, hipStream_t st);
+hipError_t launch_cell_keys(const double* pos, const float* mass, int n,
+                            Geom g, int* keys, int* vals, float4* rec,
+                            hipStream_t st);
+hipError_t launch_cell_hist(const int* keys_sorted, int n, int sbits,
+                            int* counts, hipStream_t st);
 size_t scan_tmp_ints(int n);
 hipError_t launch_scan_exclusive(const int* in, int* out, int n, int* tmp,
                                  hipStream_t st);
 int radix_blocks(int n);
+constexpr int kMaxDigitBits = 11;
 hipError_t launch_radix_pass(const int* kin, const int* vin, int* kout,
-                             int* vout, int n, int shift, int* hist,
-                             int* scan_tmp, hipStream_t st);
-hipError_t launch_gather_records(const double* pos, const float* mass,
-                                 const int* keys_sorted, const int* perm,
-                                 int n, Geom g, float4* rec, hipStream_t st);
+                             int* vout, int n, int shift, int digit_bits,
+                             int* hist, int* scan_tmp, hipStream_t st);
+hipError_t launch_gather_records(const float4* rec_in, const int* perm, int n,
+                                 float4* rec, hipStream_t st);
 hipError_t launch_gather_vec3(const float* v, const int* perm, int n,
                               float4* out, hipStream_t st);
 hipError_t launch_fill_i32(int* p, int n, int value, hipStream_t st);
