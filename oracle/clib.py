@@ -89,7 +89,9 @@ def force(pos, mass, box, r_cut, eps, poly, targets=None):
 
 
 def force_vjp(pos, mass, box, r_cut, eps, poly, g, targets=None, cut_band=None):
-    """dL/dx (nt,3) for L = sum g . a, and the pair-magnitude bound (nt,).
+    """dL/dx (nt,3) for L = sum g . a, and the error floor B (nt,): the summed
+    magnitudes of the Newtonian and grid-polynomial parts of f and f' times
+    |w| over the particle's pairs.
 
     With ``cut_band`` also returns the summed pair-term magnitude of pairs
     within a relative band |s - r_cut^2| <= cut_band r_cut^2 (nt,): the

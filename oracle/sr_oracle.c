@@ -229,8 +229,11 @@ int oracle_force(const double *pos, const float *mass, int64_t n, double box,
 /*
  * Vector-Jacobian product dL/dx_k for L = sum_i g_i . a_i, for `nt` targets
  * k (all when targets == NULL).  g: (n,3) float64 cotangents.  out: (nt,3)
- * float64.  bnorm (may be NULL): (nt,) sum_j (|f| + 2|f'| s) |w_kj|, a bound
- * on the summed pair-term magnitudes used to floor relative errors.
+ * float64.  bnorm (may be NULL): (nt,) sum_j (N + |p| + 2 s (1.5 N / (s + eps)
+ * + |p'|)) |w_kj|, N = (s + eps)^(-3/2), p the grid polynomial: the summed
+ * magnitudes of the parts of f and f' before the polynomial cancels the
+ * Newtonian term, the scale used to floor relative errors (the analogue for
+ * the VJP of the Newtonian magnitude that floors force errors).
  *
  * f' jumps at the cut-off (f itself is continuous there), so the VJP is
  * discontinuous wherever a pair sits on r_cut: an implementation that takes
@@ -269,8 +272,9 @@ int oracle_force_vjp(const double *pos, const float *mass, int64_t n,
             if (s < rc2 || edge) {
                 const double se = s + e;
                 const double newt = 1.0 / (se * sqrt(se));
-                const double f = newt - horner(c, s);
-                const double fp = -1.5 * newt / se - horner_deriv(c, s);
+                const double pv = horner(c, s), dpv = horner_deriv(c, s);
+                const double f = newt - pv;
+                const double fp = -1.5 * newt / se - dpv;
                 const double mj = (double)mass[j];
                 double w[3];
                 for (int r = 0; r < 3; ++r)
@@ -281,7 +285,7 @@ int oracle_force_vjp(const double *pos, const float *mass, int64_t n,
                 if (edge) am += mag;
                 if (s < rc2) {
                     for (int r = 0; r < 3; ++r) o[r] += f * w[r] + 2.0 * fp * dw * d[r];
-                    b += mag;
+                    b += (newt + fabs(pv) + 2.0 * s * (1.5 * newt / se + fabs(dpv))) * wn;
                 }
             }
         }

@@ -1,8 +1,9 @@
 """Parity of the HIP adjoint (VJP) kernel and the autograd wrapper with the
 float64 oracle's VJP, and with central finite differences of the oracle's
 forward sum.  Tolerance: |g - g*| <= 1e-4 max(|g*|, 0.1 B) + J, B the summed
-pair-term magnitude of that particle and J the magnitude of its pair terms
-within 1e-6 r_cut^2 of the cut-off.  f' jumps at r_cut, so a pair on the cut
+magnitude of the Newtonian and grid-polynomial parts of that particle's pair
+terms (the VJP's analogue of the force's Newtonian floor) and J the magnitude
+of its pair terms within 1e-6 r_cut^2 of the cut-off.  f' jumps at r_cut, so a pair on the cut
 contributes fully or not at all depending on the precision of the cut-off
 test (float32 in the kernel, as the paper's single-precision short-range
 force; float64 in the oracle).  J is zero for almost every particle."""
