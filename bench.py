@@ -89,7 +89,41 @@ def accuracy(w, acc, gradp, g):
             "force_raw_rel_p99": float(np.quantile(raw, 0.99)),
             "vjp_max_err": float(ge.max()),
             "vjp_particles_with_pairs_on_cut": int((~clean).sum()),
-            "metric": "|x - x*| / max(|x*|, 0.1 A), A = summed pair magnitude"}
+            "metric": "|x - x*| / max(|x*|, 0.1 F): F = summed Newtonian pair "
+                      "magnitude (forces); summed magnitude of the Newtonian and "
+                      "polynomial parts of the pair terms (VJP)"}
+
+
+def plain_comparison(hsr, torch, w, pos, mass, g_np, inside, f_ms, v_ms,
+                     with_accuracy, launches=2):
+    """The plain float32 kernels (one thread per target, no LDS staging, no
+    culling, Horner in the s basis, uncompensated sums) on the same input:
+    time per launch, interactions/s and accuracy on the same sample."""
+    dev = pos.device
+    box, rc, eps, poly = w.box, w.r_cut, w.eps, w.poly
+    ga = torch.from_numpy(g_np).to(dev)
+    acc = hsr.force_plain(pos, mass, box, rc, eps, poly)
+    gp = hsr.force_vjp_plain(pos, mass, box, rc, eps, poly, ga)
+    torch.cuda.synchronize()
+    hsr.timing_enable(True)
+    for _ in range(launches):
+        hsr.force_plain(pos, mass, box, rc, eps, poly, out=acc)
+        hsr.force_vjp_plain(pos, mass, box, rc, eps, poly, ga, out=gp)
+    torch.cuda.synchronize()
+    n_f, ms_f = hsr.timing_read(hsr.TIMER_FORCE_PLAIN)
+    n_v, ms_v = hsr.timing_read(hsr.TIMER_VJP_PLAIN)
+    hsr.timing_enable(False)
+    pf, pv = ms_f / max(n_f, 1), ms_v / max(n_v, 1)
+    out = {"force_ms": round(pf, 4), "vjp_ms": round(pv, 4),
+           "fwd_interactions_per_s": inside / (pf * 1e-3),
+           "adj_interactions_per_s": inside / (pv * 1e-3),
+           "speedup_fwd": round(pf / f_ms, 3), "speedup_adj": round(pv / v_ms, 3)}
+    if with_accuracy:
+        a = accuracy(w, acc.cpu().numpy().astype(np.float64), gp.cpu().numpy(),
+                     g_np.astype(np.float64))
+        out["force_max_err"] = a["force_max_err"]
+        out["vjp_max_err"] = a["vjp_max_err"]
+    return out
 
 
 def main() -> int:
@@ -101,6 +135,8 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the plain float32 comparison kernels")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -207,6 +243,12 @@ def main() -> int:
             "flop_per_pair": dom[2], "pairs_per_launch": inside,
             "avg_launch_ms": round(dom[3], 4)}
 
+    plain = None
+    if not args.no_plain:
+        plain = plain_comparison(hsr, torch, w, pos, mass, g_np, inside, f_ms, v_ms,
+                                 not args.no_accuracy)
+        log(f"[bench] plain float32 kernels {plain}")
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, args.cpu_seconds, g_np.astype(np.float64))
@@ -235,6 +277,7 @@ def main() -> int:
             "vjp_pct_fp32_peak": round(100 * vjp_tflops / FP32_PEAK_TFLOPS, 2),
         },
         "accuracy": acc_info,
+        "plain_fp32": plain,
         "context": "paper: 13.94 PFlops at 69.2% of peak on 1,572,864 BG/Q cores "
                    "(whole code); force kernel ~80% of BG/Q peak",
     }

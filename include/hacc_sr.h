@@ -125,6 +125,21 @@ int hacc_sr_force_vjp(const double *pos, const float *mass, int64_t n,
                       const float *grad_acc, double *out_grad_pos);
 
 /*
+ * Plain versions of hacc_sr_force and hacc_sr_force_vjp at the same
+ * accuracy, for comparison only: one thread per target, sources read from
+ * global memory over the 27 stencil cells, the cut-off as a branch, the same
+ * float32 pair arithmetic and sums in float64; no LDS tiling, culling or
+ * work list.  Same arguments, outputs and binning as the main entry points.
+ */
+int hacc_sr_force_plain(const double *pos, const float *mass, int64_t n,
+                        double box, float r_cut, float eps, const float *poly,
+                        float *out_acc);
+int hacc_sr_force_vjp_plain(const double *pos, const float *mass, int64_t n,
+                            double box, float r_cut, float eps,
+                            const float *poly, const float *grad_acc,
+                            double *out_grad_pos);
+
+/*
  * Kick of the stream-kick-stream subcycle (Sec. II, Eq. 6):
  * vel[k] += dt * acc[k] over the 3n components, in float64.
  */
@@ -158,7 +173,8 @@ int hacc_sr_count_pairs(const double *pos, int64_t n, double box, float r_cut,
 /*
  * Kernel timing with HIP events recorded on the library stream around each
  * launch of a pair kernel.  kernel: 0 = forward pair kernel, 1 = VJP pair
- * kernel, 2 = binning (all its kernels), 3 = work-list build.
+ * kernel, 2 = binning (all its kernels), 3 = work-list build, 4 = plain
+ * forward kernel, 5 = plain VJP kernel.
  * hacc_sr_timing_enable(1) starts recording (and clears earlier records);
  * hacc_sr_timing_read waits for the recorded events and returns the number
  * of launches and their summed duration in milliseconds.

@@ -5,10 +5,11 @@ The computation lives in the HIP library ``libhacc_sr.so`` (C ABI declared
 in ``include/hacc_sr.h``); this package only marshals arguments to it.
 """
 from ._lib import (load, check, strerror, grid_dim, workspace_bytes, bin,
-                   force, force_vjp, kick, stream, kick_adjoint, count_pairs,
-                   timing_enable, timing_read, release_workspace, HaccSrError,
-                   EXPORTS, LIB_PATH, TIMER_FORCE, TIMER_VJP, TIMER_BIN,
-                   TIMER_WORKLIST)
+                   force, force_vjp, force_plain, force_vjp_plain, kick, stream,
+                   kick_adjoint, count_pairs, timing_enable, timing_read,
+                   release_workspace, HaccSrError, EXPORTS, LIB_PATH,
+                   TIMER_FORCE, TIMER_VJP, TIMER_BIN, TIMER_WORKLIST,
+                   TIMER_FORCE_PLAIN, TIMER_VJP_PLAIN)
 
 
 def __getattr__(name):
@@ -20,7 +21,7 @@ def __getattr__(name):
 
 
 __all__ = ["load", "check", "strerror", "grid_dim", "workspace_bytes", "bin",
-           "force", "force_vjp", "kick", "stream", "kick_adjoint",
+           "force", "force_vjp", "force_plain", "force_vjp_plain", "kick", "stream", "kick_adjoint",
            "count_pairs", "timing_enable", "timing_read", "release_workspace",
            "HaccSrError", "EXPORTS", "LIB_PATH", "SRForce", "sr_force",
            "SKSRollout", "rollout_sks", "sks_forward"]

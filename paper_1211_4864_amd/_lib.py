@@ -22,11 +22,13 @@ EXPORTS = (
     "hacc_sr_grid_dim", "hacc_sr_workspace_bytes", "hacc_sr_set_workspace",
     "hacc_sr_bin", "hacc_sr_force", "hacc_sr_force_vjp", "hacc_sr_kick",
     "hacc_sr_stream", "hacc_sr_kick_adjoint", "hacc_sr_count_pairs",
-    "hacc_sr_timing_enable", "hacc_sr_timing_read",
+    "hacc_sr_timing_enable", "hacc_sr_timing_read", "hacc_sr_force_plain",
+    "hacc_sr_force_vjp_plain",
 )
 
 OK, EINVAL, EDOMAIN, ENOSPACE, EHIP = 0, -1, -2, -3, -4
 TIMER_FORCE, TIMER_VJP, TIMER_BIN, TIMER_WORKLIST = 0, 1, 2, 3
+TIMER_FORCE_PLAIN, TIMER_VJP_PLAIN = 4, 5
 
 
 class HaccSrError(RuntimeError):
@@ -58,6 +60,8 @@ def load():
         "hacc_sr_bin": ([P, P, I64, D, F, P, P, P], I),
         "hacc_sr_force": ([P, P, I64, D, F, F, P, P], I),
         "hacc_sr_force_vjp": ([P, P, I64, D, F, F, P, P, P], I),
+        "hacc_sr_force_plain": ([P, P, I64, D, F, F, P, P], I),
+        "hacc_sr_force_vjp_plain": ([P, P, I64, D, F, F, P, P, P], I),
         "hacc_sr_kick": ([P, P, I64, D], I),
         "hacc_sr_stream": ([P, P, I64, D, D], I),
         "hacc_sr_kick_adjoint": ([P, P, I64, D], I),
@@ -203,6 +207,43 @@ def force_vjp(pos, mass, box: float, r_cut: float, eps: float, poly, grad_acc,
                                        float(r_cut), float(eps),
                                        poly_array(poly), _ptr(grad_acc),
                                        _ptr(out)))
+    return out
+
+
+def force_plain(pos, mass, box: float, r_cut: float, eps: float, poly, out=None):
+    """The plain float32 reference kernel (comparison only)."""
+    torch = _torch()
+    n = pos.shape[0]
+    _require(pos, torch.float64, (n, 3), "pos")
+    _require(mass, torch.float32, (n,), "mass")
+    if out is None:
+        out = torch.empty((n, 3), dtype=torch.float32, device=pos.device)
+    _require(out, torch.float32, (n, 3), "out")
+    with torch.cuda.device(pos.device):
+        _bind(pos.device, n, box, r_cut)
+        check(load().hacc_sr_force_plain(_ptr(pos), _ptr(mass), n, float(box),
+                                         float(r_cut), float(eps),
+                                         poly_array(poly), _ptr(out)))
+    return out
+
+
+def force_vjp_plain(pos, mass, box: float, r_cut: float, eps: float, poly,
+                    grad_acc, out=None):
+    """The plain float32 reference VJP kernel (comparison only)."""
+    torch = _torch()
+    n = pos.shape[0]
+    _require(pos, torch.float64, (n, 3), "pos")
+    _require(mass, torch.float32, (n,), "mass")
+    _require(grad_acc, torch.float32, (n, 3), "grad_acc")
+    if out is None:
+        out = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+    _require(out, torch.float64, (n, 3), "out")
+    with torch.cuda.device(pos.device):
+        _bind(pos.device, n, box, r_cut)
+        check(load().hacc_sr_force_vjp_plain(_ptr(pos), _ptr(mass), n, float(box),
+                                             float(r_cut), float(eps),
+                                             poly_array(poly), _ptr(grad_acc),
+                                             _ptr(out)))
     return out
 
 

@@ -19,7 +19,7 @@ void* g_ws = nullptr;
 size_t g_ws_bytes = 0;
 char g_err[256] = "";
 
-constexpr int kTimers = 4;
+constexpr int kTimers = 6;
 bool g_timing = false;
 std::vector<std::pair<hipEvent_t, hipEvent_t>> g_events[kTimers];
 
@@ -195,7 +195,7 @@ int check_ws(const Layout& L) {
 // the permutation and the sorted records ended up.
 int bin_impl(const double* pos, const float* mass, int64_t n, const Geom& g,
              const Layout& L, int* cell_start, int** perm_out, float4* rec,
-             int* perm_user) {
+             int* perm_user, int** keys_out = nullptr) {
     const int nn = (int)n;
     int* ka = ws_at<int>(L.keys_a);
     int* va = ws_at<int>(L.vals_a);
@@ -221,8 +221,10 @@ int bin_impl(const double* pos, const float* mass, int64_t n, const Geom& g,
                                hipMemcpyDeviceToDevice, g_stream));
     }
     *perm_out = va;
+    if (keys_out) *keys_out = ka;
     return HACC_SR_OK;
 }
+
 
 // Builds the cost-ordered work list; returns the device counter of items.
 int worklist_impl(const int* cell_start, const Geom& g, const Layout& L,
@@ -371,6 +373,60 @@ int hacc_sr_force_vjp(const double* pos, const float* mass, int64_t n,
     return timed(1, [&] {
         HIP_TRY(launch_pair_vjp(items, L.max_items, nitems, rec, gs, cs, perm, g,
                                 P, out_grad_pos, g_stream));
+        return HACC_SR_OK;
+    });
+}
+
+int hacc_sr_force_plain(const double* pos, const float* mass, int64_t n,
+                        double box, float r_cut, float eps, const float* poly,
+                        float* out_acc) {
+    Geom g;
+    int rc = make_geom(n, box, r_cut, &g);
+    if (rc != HACC_SR_OK) return rc;
+    PairParams P;
+    if ((rc = make_params(r_cut, eps, poly, &P)) != HACC_SR_OK) return rc;
+    if (n > 0 && (!pos || !mass || !out_acc)) return HACC_SR_EINVAL;
+    if (n == 0) return HACC_SR_OK;
+    const Layout L = layout_for(n, g);
+    if ((rc = check_ws(L)) != HACC_SR_OK) return rc;
+    int* cs = ws_at<int>(L.counts);
+    float4* rec = ws_at<float4>(L.rec);
+    int *perm = nullptr, *keys = nullptr;
+    rc = bin_impl(pos, mass, n, g, L, cs, &perm, rec, nullptr, &keys);
+    if (rc != HACC_SR_OK) return rc;
+    return timed(4, [&] {
+        HIP_TRY(launch_force_plain(rec, keys, cs, perm, (int)n, g,
+                                   P, out_acc,
+                                   g_stream));
+        return HACC_SR_OK;
+    });
+}
+
+int hacc_sr_force_vjp_plain(const double* pos, const float* mass, int64_t n,
+                            double box, float r_cut, float eps,
+                            const float* poly, const float* grad_acc,
+                            double* out_grad_pos) {
+    Geom g;
+    int rc = make_geom(n, box, r_cut, &g);
+    if (rc != HACC_SR_OK) return rc;
+    PairParams P;
+    if ((rc = make_params(r_cut, eps, poly, &P)) != HACC_SR_OK) return rc;
+    if (n > 0 && (!pos || !mass || !grad_acc || !out_grad_pos))
+        return HACC_SR_EINVAL;
+    if (n == 0) return HACC_SR_OK;
+    const Layout L = layout_for(n, g);
+    if ((rc = check_ws(L)) != HACC_SR_OK) return rc;
+    int* cs = ws_at<int>(L.counts);
+    float4* rec = ws_at<float4>(L.rec);
+    float4* gs = ws_at<float4>(L.gsorted);
+    int *perm = nullptr, *keys = nullptr;
+    rc = bin_impl(pos, mass, n, g, L, cs, &perm, rec, nullptr, &keys);
+    if (rc != HACC_SR_OK) return rc;
+    HIP_TRY(launch_gather_vec3(grad_acc, perm, (int)n, gs, g_stream));
+    return timed(5, [&] {
+        HIP_TRY(launch_vjp_plain(rec, gs, keys, cs, perm, (int)n, g,
+                                 P, out_grad_pos,
+                                 g_stream));
         return HACC_SR_OK;
     });
 }

@@ -94,6 +94,15 @@ hipError_t launch_pair_vjp(const WorkItem* items, int max_items,
                            const int* perm, Geom g, PairParams p,
                            double* out_grad, hipStream_t st);
 
+// plain reference kernels (plain.hip)
+hipError_t launch_force_plain(const float4* rec, const int* keys_sorted,
+                              const int* cell_start, const int* perm, int n,
+                              Geom g, PairParams p, float* out, hipStream_t st);
+hipError_t launch_vjp_plain(const float4* rec, const float4* gsorted,
+                            const int* keys_sorted, const int* cell_start,
+                            const int* perm, int n, Geom g, PairParams p,
+                            double* out, hipStream_t st);
+
 // kick / stream (integrate.hip)
 hipError_t launch_kick(double* vel, const float* acc, int64_t m, double dt,
                        hipStream_t st);

@@ -92,6 +92,29 @@ __device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
     s = t;
 }
 
+#ifndef HSR_VCONST
+#define HSR_VCONST 1
+#endif
+// Cut-off as a branch instead of a select.  The compiler moves the whole
+// pair term under an exec mask and skips it when the source lies beyond
+// r_cut of every target of the wave: the staging cull tests the targets'
+// bounding box, whose corners are often empty, so a wave-wide skip removes
+// what the box test cannot.  Bitwise the same results as the select.
+#ifndef HSR_BRANCH_CUT
+#define HSR_BRANCH_CUT 1
+#endif
+
+// Copy of a wave-uniform constant held in a vector register.  A VALU
+// instruction reads at most one scalar register, so an FMA of two scalar
+// constants needs one of them in a vector register; the compiler would
+// otherwise copy it there again on every loop iteration.
+__device__ __forceinline__ float in_vgpr(float s) {
+    if (!HSR_VCONST) return s;
+    float v;
+    asm("v_mov_b32 %0, %1" : "=v"(v) : "s"(s));
+    return v;
+}
+
 // Wave-uniform values kept in scalar registers.
 __device__ __forceinline__ float uniform(float v) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
@@ -157,23 +180,6 @@ __device__ int build_segments(const WorkItem& it, const int* __restrict__ cs,
     return total;
 }
 
-// Segment holding tile position p (0 <= p < total): the last entry whose
-// offset is <= p.  Empty segments share offsets with the next one.
-__device__ __forceinline__ int find_segment(const Segments& sg, int p) {
-    int lo = 0;
-#pragma unroll
-    for (int step = kSeg / 2; step >= 1; step >>= 1)
-        if (sg.off[lo + step] <= p) lo += step;
-    return lo;
-}
-
-// Window position p -> sorted entry and stencil code of its cell.
-__device__ __forceinline__ int window_entry(const Segments& sg, int p, int* code) {
-    const int s = find_segment(sg, p);
-    *code = sg.code[s];
-    return sg.start[s] + (p - sg.off[s]);
-}
-
 // Record shifted from its own cell into the item frame.
 __device__ __forceinline__ float4 shift_into_frame(float4 r, int code, float Lc) {
     return make_float4(frame(r.x, (code & 15) - 1, Lc),
@@ -185,8 +191,19 @@ constexpr int kVT = HSR_VJP_TILE;     // sources per LDS tile of the VJP kernel
 constexpr int kVU = HSR_VJP_UNROLL;   // VJP sources per lane per unrolled step
 static_assert(kVT % (kItemI * kVU) == 0, "VJP tile must hold whole steps");
 
+// First segment of a round: advances the wave-uniform segment pointer seg
+// (0 before the first round) to the segment holding window position p.
+// Rounds start at increasing positions, so over an item the pointer moves
+// through the 27 segments once.
+__device__ __forceinline__ int advance_segment(const Segments& sg, int seg, int p) {
+    while (__builtin_amdgcn_readfirstlane(sg.off[seg + 1]) <= p) ++seg;
+    return seg;
+}
+
 // One tile's worth of window positions, loaded into registers: lane l holds
-// positions cursor + u * 64 + l, u < TILE / 64.
+// positions cursor + u * 64 + l, u < TILE / 64.  seg is the segment holding
+// cursor; a position's segment is found among the few segments that the
+// round spans instead of by a search of the whole table.
 template <bool WithG, int TILE>
 struct Round {
     static constexpr int kPer = TILE / kWave;
@@ -197,19 +214,30 @@ struct Round {
 };
 
 template <bool WithG, int TILE>
-__device__ __forceinline__ void load_round(const Segments& sg, int cursor,
-                                           int total,
+__device__ __forceinline__ void load_round(const Segments& sg, int seg,
+                                           int cursor, int total,
                                            const float4* __restrict__ rec,
                                            const float4* __restrict__ gsorted,
                                            Round<WithG, TILE>& R) {
     constexpr int kPer = TILE / kWave;
+    const int last = advance_segment(sg, seg, min(cursor + TILE, total) - 1);
+    int sp[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) sp[u] = seg;
+    for (int q = seg + 1; q <= last; ++q) {
+        const int o = __builtin_amdgcn_readfirstlane(sg.off[q]);
+#pragma unroll
+        for (int u = 0; u < kPer; ++u)
+            if (cursor + u * kWave + (int)threadIdx.x >= o) sp[u] = q;
+    }
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
         const int p = cursor + u * kWave + (int)threadIdx.x;
         R.k[u] = -1;
         R.code[u] = 0;
         if (p < total) {
-            R.k[u] = window_entry(sg, p, &R.code[u]);
+            R.code[u] = sg.code[sp[u]];
+            R.k[u] = sg.start[sp[u]] + (p - sg.off[sp[u]]);
             R.v[u] = rec[R.k[u]];
             if (WithG) R.g[u] = gsorted[R.k[u]];
         }
@@ -332,6 +360,7 @@ __device__ __forceinline__ void force_tile(const float4* __restrict__ src,
                                            const ForceConsts& c, float mref,
                                            float* s, float* cc) {
     const int st = KS > 0 ? KS : ks;
+    const float alpha = in_vgpr(c.alpha), b5 = in_vgpr(c.b5);
     for (int j0 = 0; j0 < nit; j0 += kMerge) {
         float tx = 0.f, ty = 0.f, tz = 0.f;
         const int lim = min(j0 + kMerge, nit);
@@ -346,18 +375,27 @@ __device__ __forceinline__ void force_tile(const float4* __restrict__ src,
                 sp = __builtin_fmaf(dy, dy, sp);
                 sp = __builtin_fmaf(dz, dz, sp);
                 const float y = __builtin_amdgcn_rsqf(sp);
-                const float t = __builtin_fmaf(sp, c.alpha, c.beta);
-                float p = __builtin_fmaf(c.b5, t, c.b4);
+                const float t = __builtin_fmaf(sp, alpha, c.beta);
+                float p = __builtin_fmaf(b5, t, c.b4);
                 p = __builtin_fmaf(p, t, c.b3);
                 p = __builtin_fmaf(p, t, c.b2);
                 p = __builtin_fmaf(p, t, c.b1);
                 p = __builtin_fmaf(p, t, c.b0);
                 const float y2 = y * y;
                 const float f = __builtin_fmaf(y2, y, -p);
-                const float mf = sp < c.rc2e ? (UNI ? f : pj.w * f) : 0.0f;
-                tx = __builtin_fmaf(mf, dx, tx);
-                ty = __builtin_fmaf(mf, dy, ty);
-                tz = __builtin_fmaf(mf, dz, tz);
+                if (HSR_BRANCH_CUT) {
+                    if (sp < c.rc2e) {
+                        const float mf = UNI ? f : pj.w * f;
+                        tx = __builtin_fmaf(mf, dx, tx);
+                        ty = __builtin_fmaf(mf, dy, ty);
+                        tz = __builtin_fmaf(mf, dz, tz);
+                    }
+                } else {
+                    const float mf = sp < c.rc2e ? (UNI ? f : pj.w * f) : 0.0f;
+                    tx = __builtin_fmaf(mf, dx, tx);
+                    ty = __builtin_fmaf(mf, dy, ty);
+                    tz = __builtin_fmaf(mf, dz, tz);
+                }
             }
         }
         if (UNI) {
@@ -396,17 +434,20 @@ __global__ __launch_bounds__(kWave, HSR_MIN_WAVES) void k_pair_force(
     float s[3] = {0.f, 0.f, 0.f}, cc[3] = {0.f, 0.f, 0.f};
 
     Round<false, kT> R;
-    if (HSR_PREFETCH) load_round(sg, 0, total, rec, rec, R);
+    int seg = 0;
+    if (HSR_PREFETCH && total > 0) load_round(sg, 0, 0, total, rec, rec, R);
     for (int cursor = 0; cursor < total; cursor += kT) {
         bool mixed;
-        if (!HSR_PREFETCH) load_round(sg, cursor, total, rec, rec, R);
+        seg = advance_segment(sg, seg, cursor);
+        if (!HSR_PREFETCH) load_round(sg, seg, cursor, total, rec, rec, R);
         const int cnt = compact_round(R, lo, hi, P.cull2, Lc, mref, tile, tile,
                                       nullptr, &mixed);
         const int cntp = padded_count(cnt, L.ks);
         for (int q = cnt + lane; q < cntp; q += kWave) tile[q] = pad;
         __syncthreads();
         if (HSR_PREFETCH && cursor + kT < total)
-            load_round(sg, cursor + kT, total, rec, rec, R);
+            load_round(sg, advance_segment(sg, seg, cursor + kT), cursor + kT,
+                       total, rec, rec, R);
         const int nit = cntp / L.ks;          // sources per lane in this tile
         const float4* src = tile + L.r;
         const bool uni = targets_equal && !mixed;
@@ -453,8 +494,10 @@ __global__ __launch_bounds__(kWave) void k_pair_count(
     unsigned long long inside = 0;
     int kept = 0;
     Round<false, kT> R;
+    int seg = 0;
     for (int cursor = 0; cursor < total; cursor += kT) {
-        load_round(sg, cursor, total, rec, rec, R);
+        seg = advance_segment(sg, seg, cursor);
+        load_round(sg, seg, cursor, total, rec, rec, R);
         bool mixed;
         const int cnt = compact_round(R, lo, hi, P.cull2, Lc, 0.0f, tile, tile, tidx,
                                       &mixed);
@@ -503,6 +546,7 @@ __device__ __forceinline__ void vjp_tile(const float4* __restrict__ srcA,
                                          float* s, float* cc) {
     const int st = KS > 0 ? KS : ks;
     const ForceConsts& c = v.f;
+    const float alpha = in_vgpr(c.alpha), b5 = in_vgpr(c.b5), q4 = in_vgpr(v.q4);
     const float mk = xk.w;
     for (int j0 = 0; j0 < nit; j0 += kMerge) {
         float tx = 0.f, ty = 0.f, tz = 0.f;
@@ -519,13 +563,13 @@ __device__ __forceinline__ void vjp_tile(const float4* __restrict__ srcA,
                 sp = __builtin_fmaf(dy, dy, sp);
                 sp = __builtin_fmaf(dz, dz, sp);
                 const float y = __builtin_amdgcn_rsqf(sp);
-                const float t = __builtin_fmaf(sp, c.alpha, c.beta);
-                float p = __builtin_fmaf(c.b5, t, c.b4);
+                const float t = __builtin_fmaf(sp, alpha, c.beta);
+                float p = __builtin_fmaf(b5, t, c.b4);
                 p = __builtin_fmaf(p, t, c.b3);
                 p = __builtin_fmaf(p, t, c.b2);
                 p = __builtin_fmaf(p, t, c.b1);
                 p = __builtin_fmaf(p, t, c.b0);
-                float q = __builtin_fmaf(v.q4, t, v.q3);
+                float q = __builtin_fmaf(q4, t, v.q3);
                 q = __builtin_fmaf(q, t, v.q2);
                 q = __builtin_fmaf(q, t, v.q1);
                 q = __builtin_fmaf(q, t, v.q0);
@@ -533,8 +577,10 @@ __device__ __forceinline__ void vjp_tile(const float4* __restrict__ srcA,
                 const float y3 = y2 * y;
                 const float y5 = y3 * y2;
                 const bool in = sp < c.rc2e;
-                const float f = in ? y3 - p : 0.0f;
-                const float f2 = in ? __builtin_fmaf(-3.0f, y5, -q) : 0.0f;
+                if (HSR_BRANCH_CUT && !in) continue;
+                const float f = (HSR_BRANCH_CUT || in) ? y3 - p : 0.0f;
+                const float f2 =
+                    (HSR_BRANCH_CUT || in) ? __builtin_fmaf(-3.0f, y5, -q) : 0.0f;
                 float wx, wy, wz;
                 if (UNI) {
                     wx = gj.x - gk.x;
@@ -598,10 +644,12 @@ __global__ __launch_bounds__(kWave, HSR_VJP_MIN_WAVES) void k_pair_vjp(
     float s[3] = {0.f, 0.f, 0.f}, cc[3] = {0.f, 0.f, 0.f};
 
     Round<true, kVT> R;
-    if (HSR_VJP_PREFETCH) load_round(sg, 0, total, rec, gsorted, R);
+    int seg = 0;
+    if (HSR_VJP_PREFETCH && total > 0) load_round(sg, 0, 0, total, rec, gsorted, R);
     for (int cursor = 0; cursor < total; cursor += kVT) {
         bool mixed;
-        if (!HSR_VJP_PREFETCH) load_round(sg, cursor, total, rec, gsorted, R);
+        seg = advance_segment(sg, seg, cursor);
+        if (!HSR_VJP_PREFETCH) load_round(sg, seg, cursor, total, rec, gsorted, R);
         const int cnt = compact_round(R, lo, hi, P.cull2, Lc, mref, tileA, tileB,
                                       nullptr, &mixed);
         const int cntp = padded_count(cnt, L.ks, kVU);
@@ -611,7 +659,8 @@ __global__ __launch_bounds__(kWave, HSR_VJP_MIN_WAVES) void k_pair_vjp(
         }
         __syncthreads();
         if (HSR_VJP_PREFETCH && cursor + kVT < total)
-            load_round(sg, cursor + kVT, total, rec, gsorted, R);
+            load_round(sg, advance_segment(sg, seg, cursor + kVT), cursor + kVT,
+                       total, rec, gsorted, R);
         const int nit = cntp / L.ks;
         const float4* srcA = tileA + L.r;
         const float4* srcB = tileB + L.r;
