@@ -40,6 +40,39 @@ WORKLOADS = {
 }
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "pair_kernels_cfg3_hbm_traffic.md")
+KERNEL_SOURCES = ("pair.hip", "common.h")
+
+
+def kernel_source_hash() -> str:
+    """sha256 over the pair kernels' sources, to tie counter readings to the
+    code they were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1211_4864_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by what the same counters read
+    for a device copy of known size), or None when the summary is missing or
+    was taken on other kernel sources."""
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            text = f.read()
+        block = text.split("```json", 1)[1].split("```", 1)[0]
+        data = json.loads(block)
+    except (OSError, IndexError, ValueError):
+        return None
+    if data.get("source_sha256") != kernel_source_hash():
+        return None
+    k = data.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("hbm_bytes_per_launch")
+
+
 def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
@@ -234,12 +267,14 @@ def main() -> int:
     fwd_tflops = FLOP_FWD * inside / (f_ms * 1e-3) / 1e12
     vjp_tflops = FLOP_VJP * inside / (v_ms * 1e-3) / 1e12
     if v_ms >= f_ms:
-        dom = ("vjp pair kernel (k_pair_vjp)", vjp_tflops, FLOP_VJP, v_ms)
+        dom = ("vjp pair kernel (k_pair_vjp)", vjp_tflops, FLOP_VJP, v_ms, "k_pair_vjp")
     else:
-        dom = ("forward pair kernel (k_pair_force)", fwd_tflops, FLOP_FWD, f_ms)
+        dom = ("forward pair kernel (k_pair_force)", fwd_tflops, FLOP_FWD, f_ms,
+               "k_pair_force")
     roof = {"bound": "alu", "kernel": dom[0], "achieved": round(dom[1], 3),
             "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(dom[1] / FP32_PEAK_TFLOPS, 4), "traffic": None,
+            "frac": round(dom[1] / FP32_PEAK_TFLOPS, 4),
+            "traffic": measured_traffic(dom[4]),
             "flop_per_pair": dom[2], "pairs_per_launch": inside,
             "avg_launch_ms": round(dom[3], 4)}
 
