@@ -128,7 +128,8 @@ int make_params(float r_cut, float eps, const float* poly, PairParams* P) {
 
 struct Layout {
     size_t keys_a, vals_a, keys_b, vals_b, counts, hist, scan_tmp, rec,
-        gsorted, cell_items, items, items_sorted, bucket_of, buckets;
+        gsorted, cell_items, items, items_sorted, bucket_of, buckets,
+        cell_window, col_cost, col_xcd;
     size_t total;
     int64_t ncell;
     int max_items;
@@ -174,7 +175,10 @@ Layout layout_for(int64_t n, const Geom& g) {
     L.items = take(sizeof(WorkItem) * (size_t)L.max_items);
     L.items_sorted = take(sizeof(WorkItem) * (size_t)L.max_items);
     L.bucket_of = take(sizeof(int) * (size_t)L.max_items);
-    L.buckets = take(sizeof(int) * 2 * kCostBuckets);
+    L.buckets = take(sizeof(int) * kOrderInts);
+    L.cell_window = take(sizeof(int) * (size_t)L.ncell);
+    L.col_cost = take(sizeof(unsigned long long) * (size_t)(g.N) * (size_t)g.N);
+    L.col_xcd = take(sizeof(int) * (size_t)(g.N) * (size_t)g.N);
     L.total = off + 256;   // slack for aligning the base pointer
     return L;
 }
@@ -237,11 +241,15 @@ int worklist_impl(const int* cell_start, const Geom& g, const Layout& L,
     int* tmp = ws_at<int>(L.scan_tmp);
     const int nc = (int)L.ncell;
     HIP_TRY(launch_fill_i32(ci + nc, 1, 0, g_stream));
-    HIP_TRY(launch_items_count(cell_start, g, ci, g_stream));
+    int* cw = ws_at<int>(L.cell_window);
+    int* cx = ws_at<int>(L.col_xcd);
+    HIP_TRY(launch_items_count(cell_start, g, ci, cw,
+                               ws_at<unsigned long long>(L.col_cost), cx,
+                               g_stream));
     HIP_TRY(launch_scan_exclusive(ci, ci, nc + 1, tmp, g_stream));
     HIP_TRY(launch_items_write(cell_start, g, ci, items, g_stream));
-    HIP_TRY(launch_items_order(items, ci + nc, L.max_items, cell_start, g, bof,
-                               bc, bc + kCostBuckets, sorted, g_stream));
+    HIP_TRY(launch_items_order(items, ci + nc, L.max_items, cw, cx, g, bof, bc,
+                               sorted, g_stream));
     *items_out = sorted;
     *n_items_dev = ci + nc;
     return HACC_SR_OK;

@@ -38,9 +38,19 @@ struct PairParams {
 struct WorkItem {
     int i_begin;      // first sorted entry of the targets
     int i_count;      // number of targets T (1..kItemI)
-    int key;          // cell index
-    int ksplit;       // lanes per target, a power of two
+    int key;          // first cell of the item's run of cells
+    short ksplit;     // lanes per target, a power of two
+    short zlen;       // cells in the run: key, key + 1, ... along z
 };
+
+// Small cells are merged into runs of up to kZRun cells along z (one item,
+// one source window of 3 x 3 x (zlen + 2) cells) when a whole aligned block
+// holds at most kItemI targets.
+#ifndef HSR_ZRUN
+#define HSR_ZRUN 2
+#endif
+constexpr int kZRun = HSR_ZRUN;
+constexpr int kMaxSegments = 9 * (kZRun + 2);   // stencil cells of a run
 
 constexpr int kItemI = 64;     // lanes of a wave
 
@@ -68,15 +78,20 @@ hipError_t launch_fill_i32(int* p, int n, int value, hipStream_t st);
 
 // work list (worklist.hip)
 constexpr int kCostBuckets = 128;
+constexpr int kXcds = 8;            // XCDs of an MI355X
+// Ints of the ordering buffer: counts and offsets of kXcds * kCostBuckets
+// buckets, then 2 kXcds + 1 list-layout entries.
+constexpr int kOrderInts = 2 * kXcds * kCostBuckets + 2 * kXcds + 1;
 hipError_t launch_items_count(const int* cell_start, Geom g, int* cell_items,
-                              hipStream_t st);
+                              int* cell_window, unsigned long long* col_cost,
+                              int* col_xcd, hipStream_t st);
 hipError_t launch_items_write(const int* cell_start, Geom g,
                               const int* cell_off, WorkItem* items,
                               hipStream_t st);
 hipError_t launch_items_order(const WorkItem* items, const int* n_items_dev,
-                              int max_items, const int* cell_start, Geom g,
-                              int* bucket_of, int* bucket_count,
-                              int* bucket_off, WorkItem* items_sorted,
+                              int max_items, const int* cell_window,
+                              const int* col_xcd, Geom g, int* bucket_of,
+                              int* buckets, WorkItem* items_sorted,
                               hipStream_t st);
 
 // pair kernels (pair.hip)

@@ -70,7 +70,8 @@ namespace {
 constexpr int kT = HSR_TILE;       // sources per LDS tile
 constexpr int kU = HSR_UNROLL;     // sources per lane per unrolled step
 constexpr int kMerge = HSR_MERGE;  // sources per lane between compensated merges
-constexpr int kSeg = 32;           // segment table entries (27 stencil cells)
+constexpr int kSeg = 64;           // segment table entries (stencil cells of a run)
+static_assert(kMaxSegments <= kSeg, "a run's stencil must fit the segment table");
 
 static_assert(kItemI == kWave, "one item per wave");
 static_assert(kT % (kItemI * kU) == 0, "tile must hold whole steps for any split");
@@ -130,29 +131,37 @@ __device__ __forceinline__ double group_sum(double v, int k) {
     return v;
 }
 
-// Coordinate shifted by `cells` cell sides into the item frame.  Sources are
-// staged with this expression, and cells == 0 leaves a coordinate unchanged,
-// so a particle meets itself at d = 0.
-__device__ __forceinline__ float frame(float rel, int cells, float Lc) {
-    return __builtin_fmaf((float)cells, Lc, rel);
+// Coordinate relative to its own cell's lower corner, shifted by `cells`
+// cell sides (a multiple of 1/2) into the item frame with one rounding.
+// Targets and sources go through this same expression, so a particle meets
+// itself at d = 0.  The item frame is centred on the item: on its cell in x
+// and y and on its run of cells in z, so coordinates stay within 1.5 cell
+// sides (2 for a run of two cells) and the float32 rounding of separations
+// stays small.
+__device__ __forceinline__ float frame(float rel, float cells, float Lc) {
+    return __builtin_fmaf(cells, Lc, rel);
 }
 
 struct Segments {
     int off[kSeg + 1];   // first tile position of each segment
     int start[kSeg];     // first sorted entry of the segment's cell
-    int code[kSeg];      // (dx+1) | (dy+1) << 4 | (dz+1) << 8
+    int code[kSeg];      // (dx+1) | (dy+1) << 4 | (dz+1) << 8, relative to the
+                         // run's first cell
 };
 
-// Builds the segment table of one item (one stencil cell per lane) and
-// returns the number of sources.  Must be called by the whole wave.
+// Builds the segment table of one item (one stencil cell per lane: the
+// 3 x 3 x (zlen + 2) cells around the item's run of cells) and returns the
+// number of sources.  Must be called by the whole wave.
 __device__ int build_segments(const WorkItem& it, const int* __restrict__ cs,
                               const Geom& g, Segments& sg) {
     const int lane = threadIdx.x;
     const int N = g.N;
     const int cz = it.key % N, cy = (it.key / N) % N, cx = it.key / (N * N);
+    const int zw = it.zlen + 2;          // window cells along z
     int cnt = 0, start = 0, code = 0;
-    if (lane < 27) {
-        const int a = lane / 9 - 1, b = (lane / 3) % 3 - 1, c = lane % 3 - 1;
+    if (lane < 9 * zw) {
+        const int ab = lane / zw;
+        const int a = ab / 3 - 1, b = ab % 3 - 1, c = lane % zw - 1;
         int x = cx + a, y = cy + b, z = cz + c;
         bool ok = true;
         if (g.periodic) {
@@ -180,11 +189,31 @@ __device__ int build_segments(const WorkItem& it, const int* __restrict__ cs,
     return total;
 }
 
+// Target record in the item frame: a target in the run's c-th cell is
+// shifted as its own record is as a source (c - zlen/2 cell sides along z,
+// -1/2 along x and y).  The run's cells are consecutive in key order, so
+// their first entries increase along the run.
+__device__ __forceinline__ float4 target_in_frame(float4 x, int ki,
+                                                  const WorkItem& it,
+                                                  const Segments& sg, float Lc) {
+    if (ki < 0) return x;
+    const int centre = 4 * (it.zlen + 2) + 1;   // segment of the run's cell 0
+    int dz = 0;
+    for (int c = 1; c < it.zlen; ++c)
+        if (ki >= sg.start[centre + c]) dz = c;
+    x.x = frame(x.x, -0.5f, Lc);
+    x.y = frame(x.y, -0.5f, Lc);
+    x.z = frame(x.z, (float)dz - 0.5f * (float)it.zlen, Lc);
+    return x;
+}
+
 // Record shifted from its own cell into the item frame.
-__device__ __forceinline__ float4 shift_into_frame(float4 r, int code, float Lc) {
-    return make_float4(frame(r.x, (code & 15) - 1, Lc),
-                       frame(r.y, ((code >> 4) & 15) - 1, Lc),
-                       frame(r.z, (code >> 8) - 1, Lc), r.w);
+// zc: half the run length, the frame's centre along z in cell sides.
+__device__ __forceinline__ float4 shift_into_frame(float4 r, int code, float Lc,
+                                                   float zc) {
+    return make_float4(frame(r.x, (float)((code & 15) - 1) - 0.5f, Lc),
+                       frame(r.y, (float)(((code >> 4) & 15) - 1) - 0.5f, Lc),
+                       frame(r.z, (float)((code >> 8) - 1) - zc, Lc), r.w);
 }
 
 constexpr int kVT = HSR_VJP_TILE;     // sources per LDS tile of the VJP kernel
@@ -260,7 +289,7 @@ __device__ __forceinline__ float box_gap2(float4 s, float4 lo, float4 hi) {
 template <bool WithG, int TILE>
 __device__ __forceinline__ int compact_round(const Round<WithG, TILE>& R, float4 lo,
                                              float4 hi, float cull2, float Lc,
-                                             float mref, float4* tileA,
+                                             float zc, float mref, float4* tileA,
                                              float4* tileB, int* tidx,
                                              bool* mixed) {
     constexpr int kPer = TILE / kWave;
@@ -272,7 +301,7 @@ __device__ __forceinline__ int compact_round(const Round<WithG, TILE>& R, float4
         bool keep = R.k[u] >= 0;
         float4 sv = make_float4(0.f, 0.f, 0.f, 0.f);
         if (keep) {
-            sv = shift_into_frame(R.v[u], R.code[u], Lc);
+            sv = shift_into_frame(R.v[u], R.code[u], Lc, zc);
             keep = box_gap2(sv, lo, hi) < cull2;
             other |= keep && sv.w != mref;
         }
@@ -422,7 +451,9 @@ __global__ __launch_bounds__(kWave, HSR_MIN_WAVES) void k_pair_force(
     const float Lc = g.Lc_f;
     const int total = build_segments(it, cs, g, sg);
     const Lanes L = lane_map(it);
-    const float4 xi = L.ki >= 0 ? rec[L.ki] : make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 xi = L.ki >= 0 ? rec[L.ki] : make_float4(0.f, 0.f, 0.f, 0.f);
+    __syncthreads();
+    xi = target_in_frame(xi, L.ki, it, sg, Lc);
     float4 lo, hi;
     target_box(xi, L.ki >= 0, &lo, &hi);
     const float mref = uniform(__shfl(xi.w, 0));
@@ -440,7 +471,8 @@ __global__ __launch_bounds__(kWave, HSR_MIN_WAVES) void k_pair_force(
         bool mixed;
         seg = advance_segment(sg, seg, cursor);
         if (!HSR_PREFETCH) load_round(sg, seg, cursor, total, rec, rec, R);
-        const int cnt = compact_round(R, lo, hi, P.cull2, Lc, mref, tile, tile,
+        const int cnt = compact_round(R, lo, hi, P.cull2, Lc, 0.5f * it.zlen, mref,
+                                      tile, tile,
                                       nullptr, &mixed);
         const int cntp = padded_count(cnt, L.ks);
         for (int q = cnt + lane; q < cntp; q += kWave) tile[q] = pad;
@@ -487,7 +519,9 @@ __global__ __launch_bounds__(kWave) void k_pair_count(
     const float Lc = g.Lc_f;
     const int total = build_segments(it, cs, g, sg);
     const Lanes L = lane_map(it);
-    const float4 xi = L.ki >= 0 ? rec[L.ki] : make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 xi = L.ki >= 0 ? rec[L.ki] : make_float4(0.f, 0.f, 0.f, 0.f);
+    __syncthreads();
+    xi = target_in_frame(xi, L.ki, it, sg, Lc);
     float4 lo, hi;
     target_box(xi, L.ki >= 0, &lo, &hi);
     __syncthreads();
@@ -499,7 +533,8 @@ __global__ __launch_bounds__(kWave) void k_pair_count(
         seg = advance_segment(sg, seg, cursor);
         load_round(sg, seg, cursor, total, rec, rec, R);
         bool mixed;
-        const int cnt = compact_round(R, lo, hi, P.cull2, Lc, 0.0f, tile, tile, tidx,
+        const int cnt = compact_round(R, lo, hi, P.cull2, Lc, 0.5f * it.zlen, 0.0f,
+                                      tile, tile, tidx,
                                       &mixed);
         kept += cnt;
         __syncthreads();
@@ -630,7 +665,9 @@ __global__ __launch_bounds__(kWave, HSR_VJP_MIN_WAVES) void k_pair_vjp(
     const float Lc = g.Lc_f;
     const int total = build_segments(it, cs, g, sg);
     const Lanes L = lane_map(it);
-    const float4 xk = L.ki >= 0 ? rec[L.ki] : make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 xk = L.ki >= 0 ? rec[L.ki] : make_float4(0.f, 0.f, 0.f, 0.f);
+    __syncthreads();
+    xk = target_in_frame(xk, L.ki, it, sg, Lc);
     const float4 gk = L.ki >= 0 ? gsorted[L.ki] : make_float4(0.f, 0.f, 0.f, 0.f);
     float4 lo, hi;
     target_box(xk, L.ki >= 0, &lo, &hi);
@@ -650,7 +687,8 @@ __global__ __launch_bounds__(kWave, HSR_VJP_MIN_WAVES) void k_pair_vjp(
         bool mixed;
         seg = advance_segment(sg, seg, cursor);
         if (!HSR_VJP_PREFETCH) load_round(sg, seg, cursor, total, rec, gsorted, R);
-        const int cnt = compact_round(R, lo, hi, P.cull2, Lc, mref, tileA, tileB,
+        const int cnt = compact_round(R, lo, hi, P.cull2, Lc, 0.5f * it.zlen, mref,
+                                      tileA, tileB,
                                       nullptr, &mixed);
         const int cntp = padded_count(cnt, L.ks, kVU);
         for (int q = cnt + lane; q < cntp; q += kWave) {

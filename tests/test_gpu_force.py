@@ -181,9 +181,46 @@ def test_pair_counts(cuda):
     keys, perm, cs, _ = binning.chaining_mesh(w.pos, w.mass, w.box, w.r_cut)
     N, _ = binning.grid(w.box, w.r_cut)
     occ = np.diff(cs).reshape(N, N, N)
-    stencil = sum(np.roll(occ, (a, b, c), (0, 1, 2)) for a in (-1, 0, 1)
-                  for b in (-1, 0, 1) for c in (-1, 0, 1))
-    # the kernel evaluates the 27-cell stencil minus the sources the staging
-    # cull proves to be out of range
-    stencil_pairs = int((occ * (stencil - 1)).sum())
-    assert inside <= cand <= stencil_pairs
+    # the kernel evaluates each item's source window (the 3 x 3 x (zlen + 2)
+    # cells around its run of cells) minus the sources the staging cull
+    # proves to be out of range
+    assert inside <= cand <= window_pairs(occ, periodic=True)
+
+
+def window_pairs(occ, periodic, zrun=4, item=64):
+    """Sum over targets of their item's window size minus one, for the run
+    rule of the work list: an aligned block of `zrun` cells along z (at most
+    N - 2 of them in a periodic box) holding at most `item` targets is one
+    run, every other cell is a run of its own."""
+    N = occ.shape[0]
+
+    def window(x, y, z0, n):
+        win = 0
+        for a in (-1, 0, 1):
+            for b in (-1, 0, 1):
+                for c in range(-1, n + 1):
+                    xx, yy, zz = x + a, y + b, z0 + c
+                    if periodic:
+                        win += occ[xx % N, yy % N, zz % N]
+                    elif 0 <= xx < N and 0 <= yy < N and 0 <= zz < N:
+                        win += occ[xx, yy, zz]
+        return int(win)
+
+    total = 0
+    for x in range(N):
+        for y in range(N):
+            col = occ[x, y]
+            for z0 in range(0, N, zrun):
+                block = min(zrun, N - z0)
+                zl = min(block, N - 2) if periodic else block
+                runs = []
+                if zl >= 2 and col[z0:z0 + zl].sum() <= item:
+                    runs.append((z0, zl))
+                    runs += [(z, 1) for z in range(z0 + zl, z0 + block)]
+                else:
+                    runs = [(z, 1) for z in range(z0, z0 + block)]
+                for z, n in runs:
+                    t = int(col[z:z + n].sum())
+                    if t:
+                        total += t * (window(x, y, z, n) - 1)
+    return total
