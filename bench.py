@@ -37,6 +37,10 @@ WORKLOADS = {
             "r_cut = 3/256, eps = 2.5e-6, 85^3 chaining cells, seed 3",
     "cfg2": "128^3 = 2.1M particles, 2000 Plummer halos (60%) + uniform, periodic, "
             "r_cut = 3/128, eps = 1e-5, 42^3 chaining cells, seed 2",
+    "cfg5": "one GPU's share of a 512^3 periodic parent: 134.2M particles in 160000 "
+            "NFW halos (70%) + uniform, plus the periodic images within 3 cells of "
+            "each face (particle overloading), open box of side 1 + 6/512, "
+            "r_cut = 3/512, eps = 6.25e-7, seed 5",
 }
 
 
@@ -172,6 +176,10 @@ def main() -> int:
                     help="skip the plain float32 comparison kernels")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--rollout", type=int, default=1,
+                    help="SKS subcycles per step; above 1 the step is the "
+                         "differentiable rollout (autograd, checkpointed) forward "
+                         "and backward")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -211,6 +219,7 @@ def main() -> int:
     else:
         acc_info = None
 
+    n_c = max(1, args.rollout)
     x = pos.clone()
     v = torch.zeros_like(x)
     acc = torch.empty((n, 3), dtype=torch.float32, device=dev)
@@ -234,6 +243,28 @@ def main() -> int:
         hsr.force_vjp(cp, mass, box, rc, eps, poly, ga, out=gtmp)
         hsr.stream(gxx, gtmp, 1.0, 0.0)
         hsr.stream(gv, gxx, 0.5 * h, 0.0)
+
+    if n_c > 1:
+        x0 = pos.clone().requires_grad_(True)
+        v0 = torch.zeros_like(pos).requires_grad_(True)
+
+        def step():  # noqa: F811  (the rollout step)
+            x0.grad = None
+            v0.grad = None
+            xf, _ = hsr.rollout_sks(x0, v0, mass, box, rc, eps, poly, h, n_c)
+            (gx * xf).sum().backward()
+
+        # in-cut-off pairs at each subcycle's force position (untimed)
+        xs, vs = pos.clone(), torch.zeros_like(pos)
+        cps = []
+        hsr.sks_forward(xs, vs, mass, box, rc, eps, poly, h, n_c, cps)
+        counts = [hsr.count_pairs(c, box, rc, eps) for c in cps]
+        cand = sum(c[0] for c in counts) / n_c
+        inside_per_force = [c[1] for c in counts]
+        inside = sum(inside_per_force) / n_c
+        del xs, vs, cps
+        log(f"[bench] rollout of {n_c} subcycles: mean in-cut-off pairs per force "
+            f"{inside:.4e}")
 
     for _ in range(args.warmup):
         step()
@@ -261,7 +292,7 @@ def main() -> int:
         torch.cuda.synchronize()
 
     ms_step = 1e3 * t_total / args.steps
-    value = 2.0 * inside / (t_total / args.steps)
+    value = 2.0 * n_c * inside / (t_total / args.steps)
     f_ms = ms_f / max(n_f, 1)
     v_ms = ms_v / max(n_v, 1)
     fwd_tflops = FLOP_FWD * inside / (f_ms * 1e-3) / 1e12
@@ -298,7 +329,10 @@ def main() -> int:
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}",
                    "n": n, "pairs_inside_rcut": inside,
                    "candidate_pairs": cand,
-                   "step": "one SKS subcycle forward + reverse (force + VJP)"},
+                   "step": ("one SKS subcycle forward + reverse (force + VJP)"
+                            if n_c == 1 else
+                            f"differentiable rollout of {n_c} SKS subcycles "
+                            f"(autograd, position checkpoints) forward + backward")},
         "roofline": roof,
         "cpu_baseline": cpu,
         "kernels": {
@@ -310,6 +344,11 @@ def main() -> int:
             "fwd_tflops": round(fwd_tflops, 3), "vjp_tflops": round(vjp_tflops, 3),
             "fwd_pct_fp32_peak": round(100 * fwd_tflops / FP32_PEAK_TFLOPS, 2),
             "vjp_pct_fp32_peak": round(100 * vjp_tflops / FP32_PEAK_TFLOPS, 2),
+            # executed rate: counted FLOP x every evaluated candidate pair
+            "fwd_executed_tflops": round(FLOP_FWD * cand / (f_ms * 1e-3) / 1e12, 3),
+            "vjp_executed_tflops": round(FLOP_VJP * cand / (v_ms * 1e-3) / 1e12, 3),
+            "useful_fraction": round(inside / cand, 4),
+            "peak_device_memory_gb": round(torch.cuda.max_memory_allocated(dev) / 1e9, 3),
         },
         "accuracy": acc_info,
         "plain_fp32": plain,
