@@ -44,7 +44,7 @@ WORKLOADS = {
 }
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "pair_kernels_cfg3_hbm_traffic.md")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "pair_kernels_cfg3_counters.md")
 KERNEL_SOURCES = ("pair.hip", "common.h")
 
 
