@@ -104,6 +104,15 @@ __device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
 #ifndef HSR_BRANCH_CUT
 #define HSR_BRANCH_CUT 1
 #endif
+// LDS reads of a step's sources issued together before any of its cut-off
+// branches (1), and also one step ahead (2), so that a wave does not wait on
+// LDS latency once per pair.
+#ifndef HSR_LDS_PIPE
+#define HSR_LDS_PIPE 1
+#endif
+#ifndef HSR_VJP_LDS_PIPE
+#define HSR_VJP_LDS_PIPE 1
+#endif
 
 // Copy of a wave-uniform constant held in a vector register.  A VALU
 // instruction reads at most one scalar register, so an FMA of two scalar
@@ -393,10 +402,25 @@ __device__ __forceinline__ void force_tile(const float4* __restrict__ src,
     for (int j0 = 0; j0 < nit; j0 += kMerge) {
         float tx = 0.f, ty = 0.f, tz = 0.f;
         const int lim = min(j0 + kMerge, nit);
+        float4 nxt[kU];
+        if (HSR_LDS_PIPE >= 2) {
+#pragma unroll
+            for (int u = 0; u < kU; ++u) nxt[u] = src[(j0 + u) * st];
+        }
         for (int jj = j0; jj < lim; jj += kU) {
+            float4 cur[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u)
+                cur[u] = HSR_LDS_PIPE >= 2 ? nxt[u]
+                                           : (HSR_LDS_PIPE ? src[(jj + u) * st]
+                                                           : float4{});
+            if (HSR_LDS_PIPE >= 2 && jj + kU < lim) {
+#pragma unroll
+                for (int u = 0; u < kU; ++u) nxt[u] = src[(jj + kU + u) * st];
+            }
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
-                const float4 pj = src[(jj + u) * st];
+                const float4 pj = HSR_LDS_PIPE ? cur[u] : src[(jj + u) * st];
                 const float dx = pj.x - xi.x;
                 const float dy = pj.y - xi.y;
                 const float dz = pj.z - xi.z;
@@ -586,11 +610,32 @@ __device__ __forceinline__ void vjp_tile(const float4* __restrict__ srcA,
     for (int j0 = 0; j0 < nit; j0 += kMerge) {
         float tx = 0.f, ty = 0.f, tz = 0.f;
         const int lim = min(j0 + kMerge, nit);
-        for (int jj = j0; jj < lim; jj += kVU) {
+        float4 nxa[kVU], nxb[kVU];
+        if (HSR_VJP_LDS_PIPE >= 2) {
 #pragma unroll
             for (int u = 0; u < kVU; ++u) {
-                const float4 pj = srcA[(jj + u) * st];
-                const float4 gj = srcB[(jj + u) * st];
+                nxa[u] = srcA[(j0 + u) * st];
+                nxb[u] = srcB[(j0 + u) * st];
+            }
+        }
+        for (int jj = j0; jj < lim; jj += kVU) {
+            float4 ca[kVU], cb[kVU];
+#pragma unroll
+            for (int u = 0; u < kVU; ++u) {
+                ca[u] = HSR_VJP_LDS_PIPE >= 2 ? nxa[u] : (HSR_VJP_LDS_PIPE ? srcA[(jj + u) * st] : float4{});
+                cb[u] = HSR_VJP_LDS_PIPE >= 2 ? nxb[u] : (HSR_VJP_LDS_PIPE ? srcB[(jj + u) * st] : float4{});
+            }
+            if (HSR_VJP_LDS_PIPE >= 2 && jj + kVU < lim) {
+#pragma unroll
+                for (int u = 0; u < kVU; ++u) {
+                    nxa[u] = srcA[(jj + kVU + u) * st];
+                    nxb[u] = srcB[(jj + kVU + u) * st];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kVU; ++u) {
+                const float4 pj = HSR_VJP_LDS_PIPE ? ca[u] : srcA[(jj + u) * st];
+                const float4 gj = HSR_VJP_LDS_PIPE ? cb[u] : srcB[(jj + u) * st];
                 const float dx = pj.x - xk.x;
                 const float dy = pj.y - xk.y;
                 const float dz = pj.z - xk.z;
