@@ -170,6 +170,41 @@ def test_edge_cases(cuda):
     assert np.allclose(moved[0], ref_moved[0], rtol=1e-5, atol=1e-5 * np.abs(base).max())
 
 
+def _mixed_masses(w, seed, frac=1.0):
+    """Masses 10^U(-1, 1) / n on a fraction of the particles (the rest keep
+    1/n): every pair kernel round with an unequal mass takes the general
+    path, the others the equal-mass one."""
+    rng = np.random.default_rng(seed)
+    m = np.full(w.n, np.float32(1.0 / w.n))
+    pick = rng.random(w.n) < frac
+    m[pick] = (10.0 ** rng.uniform(-1.0, 1.0, int(pick.sum())) / w.n).astype(np.float32)
+    w.mass = m
+    return w
+
+
+@pytest.mark.parametrize("frac,box", [(1.0, 1.0), (0.01, 1.0), (1.0, -1.0)])
+def test_force_unequal_masses(cuda, frac, box):
+    """General (unequal-mass) path of the pair kernel, alone and mixed with
+    equal-mass rounds."""
+    w = _mixed_masses(_clustered(1 << 16, 32, 40, 15, box=box), 16, frac)
+    _check(w, _gpu_acc(w, cuda))
+
+
+@pytest.mark.parametrize("cells", [4, 5, 6])
+def test_small_periodic_boxes_with_runs(cuda, cells):
+    """Boxes of 4 to 6 chaining cells per axis, sparse enough that pairs of
+    cells along z merge into runs, with runs that wrap around the periodic
+    boundary in their windows; unequal masses."""
+    fit = fit_fgrid(0.999 / (3 * cells))      # r_cut just below 1 / cells
+    assert hsr.grid_dim(1.0, fit.r_cut) == cells
+    rng = np.random.default_rng(20 + cells)
+    n = 3 * cells ** 3
+    w = Workload("runs", rng.random((n, 3)), np.full(n, np.float32(1.0 / n)), 1.0,
+                 fit.r_cut, fit.eps, fit.coeffs, fit.cell, 0, fit, {})
+    w = _mixed_masses(w, 30 + cells)
+    _check(w, _gpu_acc(w, cuda))
+
+
 def test_pair_counts(cuda):
     w = _clustered(1 << 16, 32, 40, 14)
     pos, _ = to_dev(w, cuda)

@@ -61,6 +61,20 @@ def test_vjp_clustered_full(cuda, box):
     _check(w, g, _gpu_vjp(w, g, cuda))
 
 
+@pytest.mark.parametrize("frac", [1.0, 0.01])
+def test_vjp_unequal_masses(cuda, frac):
+    """General (unequal-mass) path of the VJP kernel, alone and mixed with
+    equal-mass rounds."""
+    w = _clustered(1 << 16, 32, 40, 22)
+    rng = np.random.default_rng(23)
+    m = np.full(w.n, np.float32(1.0 / w.n))
+    pick = rng.random(w.n) < frac
+    m[pick] = (10.0 ** rng.uniform(-1.0, 1.0, int(pick.sum())) / w.n).astype(np.float32)
+    w.mass = m
+    g = cotangent(w.n, 4)
+    _check(w, g, _gpu_vjp(w, g, cuda))
+
+
 def test_vjp_cfg4_sampled_and_finite_differences(cuda):
     """128^3 clustered particles, g ~ N(0,1): VJP vs the oracle VJP on a
     stratified sample and vs central differences (h = 1e-4 cell, float64 on
