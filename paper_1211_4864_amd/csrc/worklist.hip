@@ -1,10 +1,12 @@
 // Work list for the pair kernels.  One item is one wave's worth of target
-// particles from a single chaining cell; its sources are the cell's 27-cell
-// stencil.  A cell of c targets yields floor(c/64) items of 64 targets (one
-// per lane) and at most two items for the remainder r = c mod 64: the largest
-// power of two p <= r, and r - p.  An item of T targets runs with k =
-// floor_pow2(64 / T) lanes per target, each lane taking every k-th source,
-// so a power-of-two item keeps all 64 lanes busy whatever its size.
+// particles from one run of cells: a single chaining cell, or an aligned
+// pair of cells along z that holds at most 64 targets (the run rule is in
+// run_of).  Its sources are the run's 3 x 3 x (zlen + 2) stencil cells.  A
+// run of c targets yields floor(c/64) items of 64 targets (one per lane) and
+// at most two items for the remainder r = c mod 64: the largest power of two
+// p <= r, and r - p.  An item of T targets runs with k = floor_pow2(64 / T)
+// lanes per target, each lane taking every k-th source, so a power-of-two
+// item keeps all 64 lanes busy whatever its size.
 //
 // Order of the items.  The chip has 8 XCDs, each with its own L2, and a
 // kernel's workgroup k runs on XCD k mod 8.  The cells are split into 8
