@@ -35,10 +35,10 @@
  *  - Particles are binned into a chaining mesh of N^3 cells, N =
  *    floor(|box| / r_cut), so every pair inside r_cut lies in adjacent
  *    cells.  Results are returned in the caller's particle order.
- *  - Arithmetic: pair terms in float32 on coordinates relative to the cell
- *    origin, compensated float32 accumulation; float64 only for positions,
- *    velocities and the kick/stream update.  Results are bitwise
- *    reproducible run to run.
+ *  - Arithmetic: pair terms in float32 on cell-relative coordinates shifted
+ *    into a frame centred on the work item, compensated float32
+ *    accumulation; float64 only for positions, velocities and the
+ *    kick/stream update.  Results are bitwise reproducible run to run.
  *  - Return codes: HACC_SR_OK, or one of the negative codes below.
  *    Argument checks run on the host before any GPU work, so a call that
  *    fails validation touches no device memory.  n == 0 is a valid no-op.
