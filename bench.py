@@ -45,17 +45,20 @@ WORKLOADS = {
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "pair_kernels_cfg3_counters.md")
-KERNEL_SOURCES = ("pair.hip", "common.h")
+KERNEL_SOURCES = ("pair.hip", "common.h", "worklist.hip")
 
 
 def kernel_source_hash() -> str:
-    """sha256 over the pair kernels' sources, to tie counter readings to the
-    code they were taken on."""
+    """sha256 over the code of the pair kernels and of the work list that
+    orders their items (line comments and blank lines removed), to tie
+    counter readings to the code they were taken on."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1211_4864_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_1211_4864_amd", "csrc", name)) as f:
+            lines = (re.sub(r"//.*$", "", line).rstrip() for line in f.read().split("\n"))
+            h.update("\n".join(line for line in lines if line.strip()).encode())
     return h.hexdigest()
 
 
