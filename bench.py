@@ -62,11 +62,9 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE, scaled by what the same counters read
-    for a device copy of known size), or None when the summary is missing or
-    was taken on other kernel sources."""
+def _counter_block():
+    """The JSON block of the committed rocprofv3 counter summary, or None when
+    the summary is missing or was taken on other kernel sources."""
     try:
         with open(TRAFFIC_PROFILE) as f:
             text = f.read()
@@ -76,8 +74,33 @@ def measured_traffic(kernel: str):
         return None
     if data.get("source_sha256") != kernel_source_hash():
         return None
-    k = data.get("kernels", {}).get(kernel)
+    return data
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by what the same counters read
+    for a device copy of known size), or None when the summary is missing or
+    was taken on other kernel sources."""
+    data = _counter_block()
+    k = None if data is None else data.get("kernels", {}).get(kernel)
     return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+def measured_counters(kernel: str, launch_ms: float):
+    """VALU busy, VALU lane utilisation, LDS bank-conflict share, resident
+    waves per SIMD and HBM rate of `kernel` from the committed counter summary
+    (the HBM rate divides its bytes per launch by this run's launch time), or
+    None under the same conditions as `measured_traffic`."""
+    data = _counter_block()
+    k = None if data is None else data.get("kernels", {}).get(kernel)
+    if k is None:
+        return None
+    out = {key: k.get(key) for key in ("valu_busy", "valu_lane_utilisation",
+                                       "lds_bank_conflict_frac", "waves_per_simd")}
+    b = k.get("hbm_bytes_per_launch")
+    out["hbm_tb_per_s"] = None if b is None else round(b / (launch_ms * 1e-3) / 1e12, 3)
+    return out
 
 
 def log(msg: str) -> None:
@@ -337,6 +360,8 @@ def main() -> int:
                             f"differentiable rollout of {n_c} SKS subcycles "
                             f"(autograd, position checkpoints) forward + backward")},
         "roofline": roof,
+        "counters": {"k_pair_force": measured_counters("k_pair_force", f_ms),
+                     "k_pair_vjp": measured_counters("k_pair_vjp", v_ms)},
         "cpu_baseline": cpu,
         "kernels": {
             "force_pair_ms": round(f_ms, 4), "vjp_pair_ms": round(v_ms, 4),
