@@ -35,6 +35,8 @@ WORKLOADS = {
     "cfg3": "256^3 = 16.8M particles, 20000 NFW halos (70%, masses log-uniform over "
             "4 decades, c 4-15) + uniform background, periodic unit box, "
             "r_cut = 3/256, eps = 2.5e-6, 85^3 chaining cells, seed 3",
+    "cfg3s": "cfg3 with its ten most massive halos moved into one 2x2x2-cell block "
+             "(load-balance stress: one chaining cell holds ~26000 particles), seed 3",
     "cfg2": "128^3 = 2.1M particles, 2000 Plummer halos (60%) + uniform, periodic, "
             "r_cut = 3/128, eps = 1e-5, 42^3 chaining cells, seed 2",
     "cfg5": "one GPU's share of a 512^3 periodic parent: 134.2M particles in 160000 "

@@ -97,6 +97,20 @@ def test_force_cfg3_sampled(cuda):
     assert np.all(mom <= 1e-6 * (m * np.abs(acc)).sum(0))
 
 
+def test_force_stress_block_sampled(cuda):
+    """The 256^3 workload with its ten most massive halos moved into one
+    2x2x2-cell block: one chaining cell holds ~26000 particles.  A quarter of
+    the checked targets come from the most populated cells."""
+    w = make_config("cfg3s")
+    keys = _keys(w)
+    assert np.bincount(keys).max() > 10_000
+    acc = _gpu_acc(w, cuda)
+    _check(w, acc, sample_targets(w.n, keys, 2000, seed=31))
+    m = w.mass.astype(np.float64)[:, None]
+    assert np.all(np.isfinite(acc))
+    assert np.all(np.abs((m * acc).sum(0)) <= 1e-6 * (m * np.abs(acc)).sum(0))
+
+
 def test_ghost_shell_interior_matches_periodic(cuda):
     """Open domain with a periodic-image ghost shell gives the periodic
     forces on the active particles (particle overloading)."""

@@ -15,7 +15,8 @@ import oracle
 import paper_1211_4864_amd as hsr
 from workloads import make_config, plummer_clustered, cotangent
 from workloads.configs import _finish
-from conftest import to_dev
+from conftest import to_dev, sample_targets
+from oracle import binning
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-4
@@ -58,6 +59,16 @@ def test_vjp_clustered_full(cuda, box):
     w = _clustered(1 << 16, 32, 40, 21, box=box)
     g = cotangent(w.n, 4)
     _check(w, g, _gpu_vjp(w, g, cuda))
+
+
+def test_vjp_stress_block_sampled(cuda):
+    """VJP on the 256^3 workload with ten massive halos in one 2x2x2-cell
+    block (one cell of ~26000 particles), on sampled targets, a quarter of
+    them from the most populated cells."""
+    w = make_config("cfg3s")
+    keys = binning.chaining_mesh(w.pos, w.mass, w.box, w.r_cut)[0]
+    g = cotangent(w.n, 4)
+    _check(w, g, _gpu_vjp(w, g, cuda), sample_targets(w.n, keys, 1000, seed=32))
 
 
 @pytest.mark.parametrize("frac", [1.0, 0.01])
