@@ -57,7 +57,8 @@ extern "C" {
 
 #define HACC_SR_OK 0
 #define HACC_SR_EINVAL (-1)   /* null pointer, n < 0, r_cut/eps <= 0, non-finite scalar */
-#define HACC_SR_EDOMAIN (-2)  /* periodic box < 3 r_cut, n >= 2^31, too many cells */
+#define HACC_SR_EDOMAIN (-2)  /* periodic box < 3 r_cut, n >= 2^31, too many cells,
+                                 2 min(n, cells) + n/64 >= 2^31 work items */
 #define HACC_SR_ENOSPACE (-3) /* workspace unset or smaller than required */
 #define HACC_SR_EHIP (-4)     /* HIP runtime error; text via hacc_sr_strerror */
 

@@ -3,6 +3,7 @@
 // operation on the registered stream.
 #include <hacc_sr.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -74,6 +75,10 @@ int make_geom(int64_t n, double box, float r_cut, Geom* g) {
     int N = (int)Nd;
     while (N > 1 && b / N < (double)r_cut) --N;
     if (box > 0.0 && N < 3) return HACC_SR_EDOMAIN;
+    // the work list's capacity (see layout_for) must fit an int
+    const int64_t ncell = (int64_t)N * N * N;
+    if (2 * std::min<int64_t>(n, ncell) + n / kItemI + 1 > (int64_t)INT32_MAX)
+        return HACC_SR_EDOMAIN;
     g->N = N;
     g->periodic = box > 0.0 ? 1 : 0;
     g->box = b;
@@ -265,7 +270,7 @@ const char* hacc_sr_strerror(int code) {
     switch (code) {
         case HACC_SR_OK: return "ok";
         case HACC_SR_EINVAL: return "invalid argument";
-        case HACC_SR_EDOMAIN: return "unsupported domain: periodic box below 3 r_cut, n >= 2^31 or too many cells";
+        case HACC_SR_EDOMAIN: return "unsupported domain: periodic box below 3 r_cut, n >= 2^31, too many cells or work items";
         case HACC_SR_ENOSPACE: return "workspace unset or too small";
         case HACC_SR_EHIP: return g_err[0] ? g_err : "HIP runtime error";
         default: return "unknown error code";

@@ -69,6 +69,7 @@ def _poly(vals=(0,) * 6):
     ((P(16), P(16), 10, 1.0, F(0.5), F(1e-5)), -2),        # box < 3 r_cut
     ((P(16), P(16), 2 ** 31, 1.0, F(0.1), F(1e-5)), -2),   # n >= 2^31
     ((P(16), P(16), 10, 1.0, F(1e-4), F(1e-5)), -2),       # too many cells
+    ((P(16), P(16), 1_200_000_000, 1.0, F(7.76e-4), F(1e-5)), -2),  # work items >= 2^31
 ])
 def test_force_argument_validation(lib, args, code):
     assert lib.hacc_sr_set_workspace(None, 0) == 0
