@@ -269,17 +269,21 @@ __device__ __forceinline__ void load_round(const Segments& sg, int seg,
         for (int u = 0; u < kPer; ++u)
             if (cursor + u * kWave + (int)threadIdx.x >= o) sp[u] = q;
     }
+    // Every lane loads, so the round's loads issue back to back: a lane past
+    // the end of the window re-reads the round's first source and is marked
+    // k = -1.  (Loads under per-lane branches were each preceded by a wait
+    // for the previous one.)
+    const int k0 = sg.start[seg] + (cursor - sg.off[seg]);
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
         const int p = cursor + u * kWave + (int)threadIdx.x;
-        R.k[u] = -1;
-        R.code[u] = 0;
-        if (p < total) {
-            R.code[u] = sg.code[sp[u]];
-            R.k[u] = sg.start[sp[u]] + (p - sg.off[sp[u]]);
-            R.v[u] = rec[R.k[u]];
-            if (WithG) R.g[u] = gsorted[R.k[u]];
-        }
+        const int su = sp[u];
+        const bool valid = p < total;
+        const int k = valid ? sg.start[su] + (p - sg.off[su]) : k0;
+        R.code[u] = sg.code[su];
+        R.k[u] = valid ? k : -1;
+        R.v[u] = rec[k];
+        if (WithG) R.g[u] = gsorted[k];
     }
 }
 
@@ -308,13 +312,9 @@ __device__ __forceinline__ int compact_round(const Round<WithG, TILE>& R, float4
     bool other = false;
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
-        bool keep = R.k[u] >= 0;
-        float4 sv = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (keep) {
-            sv = shift_into_frame(R.v[u], R.code[u], Lc, zc);
-            keep = box_gap2(sv, lo, hi) < cull2;
-            other |= keep && sv.w != mref;
-        }
+        const float4 sv = shift_into_frame(R.v[u], R.code[u], Lc, zc);
+        const bool keep = R.k[u] >= 0 && box_gap2(sv, lo, hi) < cull2;
+        other |= keep && sv.w != mref;
         const uint64_t m = __ballot(keep);
         if (keep) {
             const int pos = fill + __popcll(m & lt);
@@ -476,6 +476,8 @@ __global__ __launch_bounds__(kWave, HSR_MIN_WAVES) void k_pair_force(
     const float Lc = g.Lc_f;
     const int total = build_segments(it, cs, g, sg);
     const Lanes L = lane_map(it);
+    // output slot, loaded now so that its latency overlaps the rounds
+    const int dst = perm[L.ki >= 0 ? L.ki : it.i_begin];
     float4 xi = L.ki >= 0 ? rec[L.ki] : make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
     xi = target_in_frame(xi, L.ki, it, sg, Lc);
@@ -521,7 +523,7 @@ __global__ __launch_bounds__(kWave, HSR_MIN_WAVES) void k_pair_force(
     const double ay = group_sum((double)s[1] - (double)cc[1], L.ks);
     const double az = group_sum((double)s[2] - (double)cc[2], L.ks);
     if (L.ki >= 0 && L.r == 0) {
-        const int64_t o = 3 * (int64_t)perm[L.ki];
+        const int64_t o = 3 * (int64_t)dst;
         out_acc[o] = (float)ax;
         out_acc[o + 1] = (float)ay;
         out_acc[o + 2] = (float)az;
@@ -711,10 +713,12 @@ __global__ __launch_bounds__(kWave, HSR_VJP_MIN_WAVES) void k_pair_vjp(
     const float Lc = g.Lc_f;
     const int total = build_segments(it, cs, g, sg);
     const Lanes L = lane_map(it);
+    // output slot, loaded now so that its latency overlaps the rounds
+    const int dst = perm[L.ki >= 0 ? L.ki : it.i_begin];
     float4 xk = L.ki >= 0 ? rec[L.ki] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 gk = L.ki >= 0 ? gsorted[L.ki] : make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
     xk = target_in_frame(xk, L.ki, it, sg, Lc);
-    const float4 gk = L.ki >= 0 ? gsorted[L.ki] : make_float4(0.f, 0.f, 0.f, 0.f);
     float4 lo, hi;
     target_box(xk, L.ki >= 0, &lo, &hi);
     const float mref = uniform(__shfl(xk.w, 0));
@@ -762,7 +766,7 @@ __global__ __launch_bounds__(kWave, HSR_VJP_MIN_WAVES) void k_pair_vjp(
     const double gy = group_sum((double)s[1] - (double)cc[1], L.ks);
     const double gz = group_sum((double)s[2] - (double)cc[2], L.ks);
     if (L.ki >= 0 && L.r == 0) {
-        const int64_t o = 3 * (int64_t)perm[L.ki];
+        const int64_t o = 3 * (int64_t)dst;
         out_grad[o] = gx;
         out_grad[o + 1] = gy;
         out_grad[o + 2] = gz;
