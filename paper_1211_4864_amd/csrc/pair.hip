@@ -161,9 +161,11 @@ struct Segments {
 
 // Builds the segment table of one item (one stencil cell per lane: the
 // 3 x 3 x (zlen + 2) cells around the item's run of cells) and returns the
-// number of sources.  Must be called by the whole wave.
+// number of sources.  *segoff receives lane q's entry off[q] (the window
+// size for lanes past the stencil), a register copy of the table's offsets
+// for the segment searches.  Must be called by the whole wave.
 __device__ int build_segments(const WorkItem& it, const int* __restrict__ cs,
-                              const Geom& g, Segments& sg) {
+                              const Geom& g, Segments& sg, int* segoff) {
     const int lane = threadIdx.x;
     const int N = g.N;
     const int cz = it.key % N, cy = (it.key / N) % N, cx = it.key / (N * N);
@@ -190,6 +192,7 @@ __device__ int build_segments(const WorkItem& it, const int* __restrict__ cs,
     }
     const int incl = wave_incl_scan(cnt);
     const int total = __shfl(incl, kWave - 1);
+    *segoff = incl - cnt;
     if (lane < kSeg) {
         sg.off[lane] = incl - cnt;
         sg.start[lane] = start;
@@ -230,13 +233,13 @@ constexpr int kVT = HSR_VJP_TILE;     // sources per LDS tile of the VJP kernel
 constexpr int kVU = HSR_VJP_UNROLL;   // VJP sources per lane per unrolled step
 static_assert(kVT % (kItemI * kVU) == 0, "VJP tile must hold whole steps");
 
-// First segment of a round: advances the wave-uniform segment pointer seg
-// (0 before the first round) to the segment holding window position p.
-// Rounds start at increasing positions, so over an item the pointer moves
-// through the segment table once.
-__device__ __forceinline__ int advance_segment(const Segments& sg, int seg, int p) {
-    while (__builtin_amdgcn_readfirstlane(sg.off[seg + 1]) <= p) ++seg;
-    return seg;
+// Segment holding window position p (0 <= p < total): the last q with
+// off[q] <= p.  The offsets do not decrease along the lanes (segoff is lane
+// q's off[q]), so the lanes with segoff <= p form a prefix and the answer is
+// its highest lane.
+__device__ __forceinline__ int advance_segment(int segoff, int p) {
+    const uint64_t m = __ballot(segoff <= p);
+    return 63 - __builtin_clzll(m);
 }
 
 // One tile's worth of window positions, loaded into registers: lane l holds
@@ -253,18 +256,18 @@ struct Round {
 };
 
 template <bool WithG, int TILE>
-__device__ __forceinline__ void load_round(const Segments& sg, int seg,
+__device__ __forceinline__ void load_round(const Segments& sg, int segoff, int seg,
                                            int cursor, int total,
                                            const float4* __restrict__ rec,
                                            const float4* __restrict__ gsorted,
                                            Round<WithG, TILE>& R) {
     constexpr int kPer = TILE / kWave;
-    const int last = advance_segment(sg, seg, min(cursor + TILE, total) - 1);
+    const int last = advance_segment(segoff, min(cursor + TILE, total) - 1);
     int sp[kPer];
 #pragma unroll
     for (int u = 0; u < kPer; ++u) sp[u] = seg;
     for (int q = seg + 1; q <= last; ++q) {
-        const int o = __builtin_amdgcn_readfirstlane(sg.off[q]);
+        const int o = __builtin_amdgcn_readlane(segoff, q);
 #pragma unroll
         for (int u = 0; u < kPer; ++u)
             if (cursor + u * kWave + (int)threadIdx.x >= o) sp[u] = q;
@@ -474,7 +477,8 @@ __global__ __launch_bounds__(kWave, HSR_MIN_WAVES) void k_pair_force(
     const WorkItem it = items[blockIdx.x];
     const int lane = threadIdx.x;
     const float Lc = g.Lc_f;
-    const int total = build_segments(it, cs, g, sg);
+    int segoff;
+    const int total = build_segments(it, cs, g, sg, &segoff);
     const Lanes L = lane_map(it);
     // output slot, loaded now so that its latency overlaps the rounds
     const int dst = perm[L.ki >= 0 ? L.ki : it.i_begin];
@@ -493,11 +497,11 @@ __global__ __launch_bounds__(kWave, HSR_MIN_WAVES) void k_pair_force(
 
     Round<false, kT> R;
     int seg = 0;
-    if (HSR_PREFETCH && total > 0) load_round(sg, 0, 0, total, rec, rec, R);
+    if (HSR_PREFETCH && total > 0) load_round(sg, segoff, 0, 0, total, rec, rec, R);
     for (int cursor = 0; cursor < total; cursor += kT) {
         bool mixed;
-        seg = advance_segment(sg, seg, cursor);
-        if (!HSR_PREFETCH) load_round(sg, seg, cursor, total, rec, rec, R);
+        seg = advance_segment(segoff, cursor);
+        if (!HSR_PREFETCH) load_round(sg, segoff, seg, cursor, total, rec, rec, R);
         const int cnt = compact_round(R, lo, hi, P.cull2, Lc, 0.5f * it.zlen, mref,
                                       tile, tile,
                                       nullptr, &mixed);
@@ -505,7 +509,7 @@ __global__ __launch_bounds__(kWave, HSR_MIN_WAVES) void k_pair_force(
         for (int q = cnt + lane; q < cntp; q += kWave) tile[q] = pad;
         __syncthreads();
         if (HSR_PREFETCH && cursor + kT < total)
-            load_round(sg, advance_segment(sg, seg, cursor + kT), cursor + kT,
+            load_round(sg, segoff, advance_segment(segoff, cursor + kT), cursor + kT,
                        total, rec, rec, R);
         const int nit = cntp / L.ks;          // sources per lane in this tile
         const float4* src = tile + L.r;
@@ -544,7 +548,8 @@ __global__ __launch_bounds__(kWave) void k_pair_count(
     if ((int)blockIdx.x >= *n_items_dev) return;
     const WorkItem it = items[blockIdx.x];
     const float Lc = g.Lc_f;
-    const int total = build_segments(it, cs, g, sg);
+    int segoff;
+    const int total = build_segments(it, cs, g, sg, &segoff);
     const Lanes L = lane_map(it);
     float4 xi = L.ki >= 0 ? rec[L.ki] : make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
@@ -557,8 +562,8 @@ __global__ __launch_bounds__(kWave) void k_pair_count(
     Round<false, kT> R;
     int seg = 0;
     for (int cursor = 0; cursor < total; cursor += kT) {
-        seg = advance_segment(sg, seg, cursor);
-        load_round(sg, seg, cursor, total, rec, rec, R);
+        seg = advance_segment(segoff, cursor);
+        load_round(sg, segoff, seg, cursor, total, rec, rec, R);
         bool mixed;
         const int cnt = compact_round(R, lo, hi, P.cull2, Lc, 0.5f * it.zlen, 0.0f,
                                       tile, tile, tidx,
@@ -711,7 +716,8 @@ __global__ __launch_bounds__(kWave, HSR_VJP_MIN_WAVES) void k_pair_vjp(
     const WorkItem it = items[blockIdx.x];
     const int lane = threadIdx.x;
     const float Lc = g.Lc_f;
-    const int total = build_segments(it, cs, g, sg);
+    int segoff;
+    const int total = build_segments(it, cs, g, sg, &segoff);
     const Lanes L = lane_map(it);
     // output slot, loaded now so that its latency overlaps the rounds
     const int dst = perm[L.ki >= 0 ? L.ki : it.i_begin];
@@ -732,11 +738,11 @@ __global__ __launch_bounds__(kWave, HSR_VJP_MIN_WAVES) void k_pair_vjp(
 
     Round<true, kVT> R;
     int seg = 0;
-    if (HSR_VJP_PREFETCH && total > 0) load_round(sg, 0, 0, total, rec, gsorted, R);
+    if (HSR_VJP_PREFETCH && total > 0) load_round(sg, segoff, 0, 0, total, rec, gsorted, R);
     for (int cursor = 0; cursor < total; cursor += kVT) {
         bool mixed;
-        seg = advance_segment(sg, seg, cursor);
-        if (!HSR_VJP_PREFETCH) load_round(sg, seg, cursor, total, rec, gsorted, R);
+        seg = advance_segment(segoff, cursor);
+        if (!HSR_VJP_PREFETCH) load_round(sg, segoff, seg, cursor, total, rec, gsorted, R);
         const int cnt = compact_round(R, lo, hi, P.cull2, Lc, 0.5f * it.zlen, mref,
                                       tileA, tileB,
                                       nullptr, &mixed);
@@ -747,7 +753,7 @@ __global__ __launch_bounds__(kWave, HSR_VJP_MIN_WAVES) void k_pair_vjp(
         }
         __syncthreads();
         if (HSR_VJP_PREFETCH && cursor + kVT < total)
-            load_round(sg, advance_segment(sg, seg, cursor + kVT), cursor + kVT,
+            load_round(sg, segoff, advance_segment(segoff, cursor + kVT), cursor + kVT,
                        total, rec, gsorted, R);
         const int nit = cntp / L.ks;
         const float4* srcA = tileA + L.r;
