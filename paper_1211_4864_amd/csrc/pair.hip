@@ -262,15 +262,20 @@ __device__ __forceinline__ void load_round(const Segments& sg, int segoff, int s
                                            const float4* __restrict__ gsorted,
                                            Round<WithG, TILE>& R) {
     constexpr int kPer = TILE / kWave;
-    const int last = advance_segment(segoff, min(cursor + TILE, total) - 1);
+    // Segment of each lane's position, slot by slot: the segments that start
+    // inside a slot of 64 positions are the only ones that can change it.
     int sp[kPer];
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) sp[u] = seg;
-    for (int q = seg + 1; q <= last; ++q) {
-        const int o = __builtin_amdgcn_readlane(segoff, q);
-#pragma unroll
-        for (int u = 0; u < kPer; ++u)
-            if (cursor + u * kWave + (int)threadIdx.x >= o) sp[u] = q;
+    for (int u = 0; u < kPer; ++u) {
+        const int b = cursor + u * kWave;
+        int s = seg;
+        if (b < total) {
+            s = advance_segment(segoff, b);
+            const int s1 = advance_segment(segoff, min(b + kWave, total) - 1);
+            for (int q = s + 1; q <= s1; ++q)
+                if (b + (int)threadIdx.x >= __builtin_amdgcn_readlane(segoff, q)) s = q;
+        }
+        sp[u] = s;
     }
     // Every lane loads, so the round's loads issue back to back: a lane past
     // the end of the window re-reads the round's first source and is marked
