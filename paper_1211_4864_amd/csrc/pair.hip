@@ -237,15 +237,14 @@ static_assert(kVT % (kItemI * kVU) == 0, "VJP tile must hold whole steps");
 // off[q] <= p.  The offsets do not decrease along the lanes (segoff is lane
 // q's off[q]), so the lanes with segoff <= p form a prefix and the answer is
 // its highest lane.
-__device__ __forceinline__ int advance_segment(int segoff, int p) {
+__device__ __forceinline__ int segment_of(int segoff, int p) {
     const uint64_t m = __ballot(segoff <= p);
     return 63 - __builtin_clzll(m);
 }
 
 // One tile's worth of window positions, loaded into registers: lane l holds
 // positions cursor + u * 64 + l, u < TILE / 64.  seg is the segment holding
-// cursor; a position's segment is found among the few segments that the
-// round spans instead of by a search of the whole table.
+// cursor.
 template <bool WithG, int TILE>
 struct Round {
     static constexpr int kPer = TILE / kWave;
@@ -270,8 +269,8 @@ __device__ __forceinline__ void load_round(const Segments& sg, int segoff, int s
         const int b = cursor + u * kWave;
         int s = seg;
         if (b < total) {
-            s = advance_segment(segoff, b);
-            const int s1 = advance_segment(segoff, min(b + kWave, total) - 1);
+            s = segment_of(segoff, b);
+            const int s1 = segment_of(segoff, min(b + kWave, total) - 1);
             for (int q = s + 1; q <= s1; ++q)
                 if (b + (int)threadIdx.x >= __builtin_amdgcn_readlane(segoff, q)) s = q;
         }
@@ -505,7 +504,7 @@ __global__ __launch_bounds__(kWave, HSR_MIN_WAVES) void k_pair_force(
     if (HSR_PREFETCH && total > 0) load_round(sg, segoff, 0, 0, total, rec, rec, R);
     for (int cursor = 0; cursor < total; cursor += kT) {
         bool mixed;
-        seg = advance_segment(segoff, cursor);
+        seg = segment_of(segoff, cursor);
         if (!HSR_PREFETCH) load_round(sg, segoff, seg, cursor, total, rec, rec, R);
         const int cnt = compact_round(R, lo, hi, P.cull2, Lc, 0.5f * it.zlen, mref,
                                       tile, tile,
@@ -514,7 +513,7 @@ __global__ __launch_bounds__(kWave, HSR_MIN_WAVES) void k_pair_force(
         for (int q = cnt + lane; q < cntp; q += kWave) tile[q] = pad;
         __syncthreads();
         if (HSR_PREFETCH && cursor + kT < total)
-            load_round(sg, segoff, advance_segment(segoff, cursor + kT), cursor + kT,
+            load_round(sg, segoff, segment_of(segoff, cursor + kT), cursor + kT,
                        total, rec, rec, R);
         const int nit = cntp / L.ks;          // sources per lane in this tile
         const float4* src = tile + L.r;
@@ -567,7 +566,7 @@ __global__ __launch_bounds__(kWave) void k_pair_count(
     Round<false, kT> R;
     int seg = 0;
     for (int cursor = 0; cursor < total; cursor += kT) {
-        seg = advance_segment(segoff, cursor);
+        seg = segment_of(segoff, cursor);
         load_round(sg, segoff, seg, cursor, total, rec, rec, R);
         bool mixed;
         const int cnt = compact_round(R, lo, hi, P.cull2, Lc, 0.5f * it.zlen, 0.0f,
@@ -746,7 +745,7 @@ __global__ __launch_bounds__(kWave, HSR_VJP_MIN_WAVES) void k_pair_vjp(
     if (HSR_VJP_PREFETCH && total > 0) load_round(sg, segoff, 0, 0, total, rec, gsorted, R);
     for (int cursor = 0; cursor < total; cursor += kVT) {
         bool mixed;
-        seg = advance_segment(segoff, cursor);
+        seg = segment_of(segoff, cursor);
         if (!HSR_VJP_PREFETCH) load_round(sg, segoff, seg, cursor, total, rec, gsorted, R);
         const int cnt = compact_round(R, lo, hi, P.cull2, Lc, 0.5f * it.zlen, mref,
                                       tileA, tileB,
@@ -758,7 +757,7 @@ __global__ __launch_bounds__(kWave, HSR_VJP_MIN_WAVES) void k_pair_vjp(
         }
         __syncthreads();
         if (HSR_VJP_PREFETCH && cursor + kVT < total)
-            load_round(sg, segoff, advance_segment(segoff, cursor + kVT), cursor + kVT,
+            load_round(sg, segoff, segment_of(segoff, cursor + kVT), cursor + kVT,
                        total, rec, gsorted, R);
         const int nit = cntp / L.ks;
         const float4* srcA = tileA + L.r;
