@@ -155,7 +155,7 @@ __device__ __forceinline__ float frame(float rel, float cells, float Lc) {
 struct Segments {
     int off[kSeg + 1];   // first tile position of each segment
     int start[kSeg];     // first sorted entry of the segment's cell
-    int code[kSeg];      // (dx+1) | (dy+1) << 4 | (dz+1) << 8, relative to the
+    int code[kSeg];      // (dx+1) | (dy+1) << 8 | (dz+1) << 16, relative to the
                          // run's first cell
 };
 
@@ -188,7 +188,7 @@ __device__ int build_segments(const WorkItem& it, const int* __restrict__ cs,
             start = cs[key];
             cnt = cs[key + 1] - start;
         }
-        code = (a + 1) | ((b + 1) << 4) | ((c + 1) << 8);
+        code = (a + 1) | ((b + 1) << 8) | ((c + 1) << 16);
     }
     const int incl = wave_incl_scan(cnt);
     const int total = __shfl(incl, kWave - 1);
@@ -224,9 +224,10 @@ __device__ __forceinline__ float4 target_in_frame(float4 x, int ki,
 // zc: half the run length, the frame's centre along z in cell sides.
 __device__ __forceinline__ float4 shift_into_frame(float4 r, int code, float Lc,
                                                    float zc) {
-    return make_float4(frame(r.x, (float)((code & 15) - 1) - 0.5f, Lc),
-                       frame(r.y, (float)(((code >> 4) & 15) - 1) - 0.5f, Lc),
-                       frame(r.z, (float)((code >> 8) - 1) - zc, Lc), r.w);
+    // one byte per axis, so that each converts to float in one instruction
+    return make_float4(frame(r.x, (float)(code & 255) - 1.5f, Lc),
+                       frame(r.y, (float)((code >> 8) & 255) - 1.5f, Lc),
+                       frame(r.z, (float)((code >> 16) & 255) - (1.0f + zc), Lc), r.w);
 }
 
 constexpr int kVT = HSR_VJP_TILE;     // sources per LDS tile of the VJP kernel
