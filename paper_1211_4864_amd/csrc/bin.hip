@@ -284,6 +284,101 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(
     }
 }
 
+// The same pass with the block's keys first placed in LDS in their sorted
+// order (a stable local counting sort of the 4096-key tile), then written
+// out in that order: each digit's keys of the block go to consecutive
+// global slots, so the writes are runs instead of one scattered element per
+// lane.  Needs 3 * 2^DB + 4 * 2^DB + 2 * 4096 ints of LDS; used for DB <= 10.
+template <int DB>
+__global__ __launch_bounds__(kBlock) void k_radix_scatter_staged(
+    const int* __restrict__ kin, const int* __restrict__ vin,
+    int* __restrict__ kout, int* __restrict__ vout, int n, int shift,
+    const int* __restrict__ offs, int nblocks) {
+    constexpr int R = 1 << DB;
+    constexpr int kW = kBlock / kWave;
+    constexpr int kPerT = R / kBlock;   // digits per thread
+    static_assert(kPerT >= 1, "at least one digit per thread");
+    __shared__ int base_d[R];     // global offset of this block's digit d
+    __shared__ int loc_d[R];      // first tile slot of digit d in this block
+    __shared__ int run_d[R];      // digit d entries already placed by this block
+    __shared__ int wcnt[kW][R];
+    __shared__ int part[kBlock];
+    __shared__ int skey[kTile];
+    __shared__ int sval[kTile];
+    // This block's count of each digit follows from the scanned offsets
+    // (digit-major over the blocks); a block scan gives the tile slots.
+    const int64_t flat = (int64_t)R * nblocks;
+    int cnt[kPerT];
+    int sum = 0;
+#pragma unroll
+    for (int j = 0; j < kPerT; ++j) {
+        const int d = threadIdx.x * kPerT + j;
+        const int64_t idx = (int64_t)d * nblocks + blockIdx.x;
+        const int o = offs[idx];
+        const int nx = idx + 1 < flat ? offs[idx + 1] : n;
+        base_d[d] = o;
+        run_d[d] = 0;
+        cnt[j] = nx - o;
+        sum += cnt[j];
+    }
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    for (int s = 1; s < kBlock; s <<= 1) {      // inclusive scan of the sums
+        const int v = threadIdx.x >= s ? part[threadIdx.x - s] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int acc = part[threadIdx.x] - sum;
+#pragma unroll
+    for (int j = 0; j < kPerT; ++j) {
+        loc_d[threadIdx.x * kPerT + j] = acc;
+        acc += cnt[j];
+    }
+    const int w = threadIdx.x / kWave;
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    for (int it = 0; it < kItems; ++it) {
+        for (int q = threadIdx.x; q < R; q += kBlock)
+#pragma unroll
+            for (int v = 0; v < kW; ++v) wcnt[v][q] = 0;
+        __syncthreads();
+        const int64_t e = base + it * kBlock + threadIdx.x;
+        const bool active = e < n;
+        const int key = active ? kin[e] : 0;
+        const int val = active ? vin[e] : 0;
+        const unsigned d = ((unsigned)key >> shift) & (unsigned)(R - 1);
+        const uint64_t pm = peers<DB>(d, active);
+        const int rank = __popcll(pm & lanemask_lt());
+        if (active && rank == 0) wcnt[w][d] = __popcll(pm);
+        __syncthreads();
+        for (int t = threadIdx.x; t < R; t += kBlock) {
+            int a = run_d[t];
+#pragma unroll
+            for (int v = 0; v < kW; ++v) {
+                const int c = wcnt[v][t];
+                wcnt[v][t] = a;
+                a += c;
+            }
+            run_d[t] = a;
+        }
+        __syncthreads();
+        if (active) {
+            const int slot = loc_d[d] + wcnt[w][d] + rank;
+            skey[slot] = key;
+            sval[slot] = val;
+        }
+        __syncthreads();
+    }
+    const int m = (int)min((int64_t)kTile, (int64_t)n - base);
+    for (int i = threadIdx.x; i < m; i += kBlock) {
+        const int key = skey[i];
+        const unsigned d = ((unsigned)key >> shift) & (unsigned)(R - 1);
+        const int dst = base_d[d] + (i - loc_d[d]);
+        kout[dst] = key;
+        vout[dst] = sval[i];
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_gather_records(
     const float4* __restrict__ rec_in, const int* __restrict__ perm, int n,
     float4* __restrict__ rec) {
@@ -352,8 +447,12 @@ hipError_t radix_pass(const int* kin, const int* vin, int* kout, int* vout,
                        shift, hist, nb);
     hipError_t e = launch_scan_exclusive(hist, hist, (1 << DB) * nb, scan_tmp, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_radix_scatter<DB>, dim3(nb), dim3(kBlock), 0, st, kin,
-                       vin, kout, vout, n, shift, (const int*)hist, nb);
+    if constexpr (DB <= 10)
+        hipLaunchKernelGGL(k_radix_scatter_staged<DB>, dim3(nb), dim3(kBlock), 0, st,
+                           kin, vin, kout, vout, n, shift, (const int*)hist, nb);
+    else
+        hipLaunchKernelGGL(k_radix_scatter<DB>, dim3(nb), dim3(kBlock), 0, st, kin,
+                           vin, kout, vout, n, shift, (const int*)hist, nb);
     return hipGetLastError();
 }
 }  // namespace
