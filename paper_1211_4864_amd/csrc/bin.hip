@@ -288,7 +288,10 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(
 // order (a stable local counting sort of the 4096-key tile), then written
 // out in that order: each digit's keys of the block go to consecutive
 // global slots, so the writes are runs instead of one scattered element per
-// lane.  Needs 3 * 2^DB + 4 * 2^DB + 2 * 4096 ints of LDS; used for DB <= 10.
+// lane.  Wave w ranks the keys w * 1024 .. w * 1024 + 1023 of the tile, 64 at
+// a time, against its own digit counters; one prefix over the waves then
+// places every key.  Needs 2^DB * (2 + 2 * kW) + 2 * 4096 ints of LDS; used
+// for DB <= 10.
 template <int DB>
 __global__ __launch_bounds__(kBlock) void k_radix_scatter_staged(
     const int* __restrict__ kin, const int* __restrict__ vin,
@@ -296,12 +299,12 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter_staged(
     const int* __restrict__ offs, int nblocks) {
     constexpr int R = 1 << DB;
     constexpr int kW = kBlock / kWave;
-    constexpr int kPerT = R / kBlock;   // digits per thread
+    constexpr int kPerW = kTile / kW / kWave;   // keys per lane
+    constexpr int kPerT = R / kBlock;           // digits per thread
     static_assert(kPerT >= 1, "at least one digit per thread");
     __shared__ int base_d[R];     // global offset of this block's digit d
     __shared__ int loc_d[R];      // first tile slot of digit d in this block
-    __shared__ int run_d[R];      // digit d entries already placed by this block
-    __shared__ int wcnt[kW][R];
+    __shared__ int cw[kW][R];     // per wave: digit counts, then their prefix
     __shared__ int part[kBlock];
     __shared__ int skey[kTile];
     __shared__ int sval[kTile];
@@ -317,9 +320,10 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter_staged(
         const int o = offs[idx];
         const int nx = idx + 1 < flat ? offs[idx + 1] : n;
         base_d[d] = o;
-        run_d[d] = 0;
         cnt[j] = nx - o;
         sum += cnt[j];
+#pragma unroll
+        for (int v = 0; v < kW; ++v) cw[v][d] = 0;
     }
     part[threadIdx.x] = sum;
     __syncthreads();
@@ -335,46 +339,60 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter_staged(
         loc_d[threadIdx.x * kPerT + j] = acc;
         acc += cnt[j];
     }
+    // rank of each key among the equal digits before it in this wave's keys
     const int w = threadIdx.x / kWave;
-    const int64_t base = (int64_t)blockIdx.x * kTile;
-    for (int it = 0; it < kItems; ++it) {
-        for (int q = threadIdx.x; q < R; q += kBlock)
+    const int64_t first = (int64_t)blockIdx.x * kTile + (int64_t)w * (kPerW * kWave) +
+                          lane_id();
+    int key[kPerW], val[kPerW], rk[kPerW];
 #pragma unroll
-            for (int v = 0; v < kW; ++v) wcnt[v][q] = 0;
-        __syncthreads();
-        const int64_t e = base + it * kBlock + threadIdx.x;
+    for (int r = 0; r < kPerW; ++r) {
+        const int64_t e = first + r * kWave;
         const bool active = e < n;
-        const int key = active ? kin[e] : 0;
-        const int val = active ? vin[e] : 0;
-        const unsigned d = ((unsigned)key >> shift) & (unsigned)(R - 1);
+        key[r] = active ? kin[e] : 0;
+        val[r] = active ? vin[e] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < kPerW; ++r) {
+        const bool active = first + r * kWave < n;
+        const unsigned d = ((unsigned)key[r] >> shift) & (unsigned)(R - 1);
         const uint64_t pm = peers<DB>(d, active);
         const int rank = __popcll(pm & lanemask_lt());
-        if (active && rank == 0) wcnt[w][d] = __popcll(pm);
-        __syncthreads();
-        for (int t = threadIdx.x; t < R; t += kBlock) {
-            int a = run_d[t];
-#pragma unroll
-            for (int v = 0; v < kW; ++v) {
-                const int c = wcnt[v][t];
-                wcnt[v][t] = a;
-                a += c;
-            }
-            run_d[t] = a;
-        }
-        __syncthreads();
-        if (active) {
-            const int slot = loc_d[d] + wcnt[w][d] + rank;
-            skey[slot] = key;
-            sval[slot] = val;
-        }
-        __syncthreads();
+        rk[r] = active ? cw[w][d] + rank : 0;
+        // A wave's LDS accesses complete in program order; the barriers keep
+        // the compiler from moving the counter update across the reads.
+        __builtin_amdgcn_wave_barrier();
+        if (active && rank == 0) cw[w][d] += __popcll(pm);
+        __builtin_amdgcn_wave_barrier();
     }
+    __syncthreads();
+    // per digit: exclusive prefix over the waves
+    for (int d = threadIdx.x; d < R; d += kBlock) {
+        int a = 0;
+#pragma unroll
+        for (int v = 0; v < kW; ++v) {
+            const int c = cw[v][d];
+            cw[v][d] = a;
+            a += c;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kPerW; ++r) {
+        if (first + r * kWave < n) {
+            const unsigned d = ((unsigned)key[r] >> shift) & (unsigned)(R - 1);
+            const int slot = loc_d[d] + cw[w][d] + rk[r];
+            skey[slot] = key[r];
+            sval[slot] = val[r];
+        }
+    }
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kTile;
     const int m = (int)min((int64_t)kTile, (int64_t)n - base);
     for (int i = threadIdx.x; i < m; i += kBlock) {
-        const int key = skey[i];
-        const unsigned d = ((unsigned)key >> shift) & (unsigned)(R - 1);
+        const int k = skey[i];
+        const unsigned d = ((unsigned)k >> shift) & (unsigned)(R - 1);
         const int dst = base_d[d] + (i - loc_d[d]);
-        kout[dst] = key;
+        kout[dst] = k;
         vout[dst] = sval[i];
     }
 }
