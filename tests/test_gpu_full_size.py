@@ -1,0 +1,67 @@
+"""Parity at the full one-GPU share: the 512^3 NFW-clustered parent's
+periodic share plus its 3-cell ghost shell (139M particles, open box), the
+shape of the full-size rollout benchmark.  Forward and VJP are checked
+against the float64 oracle on sampled targets: random active particles and
+particles of the most populated cells.  Tolerances as in the other parity
+tests (forces 1e-5, VJP 1e-4, relative error floored by the summed pair
+magnitudes)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1211_4864_amd as hsr
+from workloads import make_config, cotangent
+from conftest import to_dev
+
+pytestmark = pytest.mark.gpu
+TOL_FORCE = 1e-5
+TOL_VJP = 1e-4
+BAND = 1e-6
+
+
+def _targets(w, k_rand=1500, k_dense=500, seed=51):
+    rng = np.random.default_rng(seed)
+    N = hsr.grid_dim(w.box, w.r_cut)
+    c = np.clip(np.floor(w.pos * (N / abs(w.box))), 0, N - 1).astype(np.int64)
+    key = (c[:, 0] * N + c[:, 1]) * N + c[:, 2]
+    top = np.argsort(-np.bincount(key, minlength=N ** 3))[:8]
+    dense = np.flatnonzero(np.isin(key, top))
+    dense = rng.choice(dense, min(k_dense, dense.size), replace=False)
+    pick = rng.choice(w.meta["n_active"], k_rand, replace=False)
+    return np.unique(np.concatenate([pick, dense]))
+
+
+def test_cfg5_full_size_sampled(cuda):
+    w = make_config("cfg5")
+    tg = _targets(w)
+    print(f"cfg5 full size: n={w.n}, {tg.size} checked targets", flush=True)
+    pos, mass = to_dev(w, cuda)
+    g = cotangent(w.n, 4)
+    idx = torch.from_numpy(tg).to(cuda)
+    acc = hsr.force(pos, mass, w.box, w.r_cut, w.eps, w.poly)
+    a = acc[idx].cpu().numpy().astype(np.float64)
+    finite_a = bool(torch.isfinite(acc).all())
+    del acc
+    gt = torch.from_numpy(g).to(cuda)
+    gpos = hsr.force_vjp(pos, mass, w.box, w.r_cut, w.eps, w.poly, gt)
+    gp = gpos[idx].cpu().numpy()
+    finite_g = bool(torch.isfinite(gpos).all())
+    del gpos, gt, pos, mass
+    torch.cuda.synchronize()
+    assert finite_a and finite_g
+
+    ref, an, _ = oracle.force(w.pos, w.mass, w.box, w.r_cut, w.eps, w.poly, targets=tg)
+    err = oracle.rel_err_floored(a, ref, an)
+    print(f"cfg5 force max err {err.max():.3e}", flush=True)
+    assert err.max() <= TOL_FORCE
+
+    vref, bn, amb = oracle.force_vjp(w.pos, w.mass, w.box, w.r_cut, w.eps, w.poly,
+                                     g.astype(np.float64), targets=tg, cut_band=BAND)
+    dev = np.linalg.norm(gp - vref, axis=1)
+    assert np.all(dev <= TOL_VJP * np.maximum(np.linalg.norm(vref, axis=1), 0.1 * bn) + amb)
+    clean = amb == 0.0
+    verr = oracle.rel_err_floored(gp[clean], vref[clean], bn[clean])
+    print(f"cfg5 vjp max err off the cut {verr.max():.3e} "
+          f"(on the cut: {(~clean).sum()})", flush=True)
+    assert verr.max() <= TOL_VJP
