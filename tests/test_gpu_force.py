@@ -126,6 +126,27 @@ def test_ghost_shell_interior_matches_periodic(cuda):
     assert oracle.rel_err_floored(a_per, ref, an).max() <= TOL
 
 
+def test_runs_on_the_callers_stream(cuda):
+    """The library launches on torch's current stream: results on a side
+    stream equal those on the default stream, and the side stream's work
+    is ordered after the inputs it waits for."""
+    w = _clustered(1 << 15, 64, 30, 17)
+    a_default = _gpu_acc(w, cuda)
+    side = torch.cuda.Stream(device=cuda)          # default priority
+    pos, mass = to_dev(w, cuda)
+    side.wait_stream(torch.cuda.current_stream(cuda))
+    with torch.cuda.stream(side):
+        acc = hsr.force(pos, mass, w.box, w.r_cut, w.eps, w.poly)
+        g = torch.ones((w.n, 3), dtype=torch.float32, device=cuda)
+        gpos = hsr.force_vjp(pos, mass, w.box, w.r_cut, w.eps, w.poly, g)
+    side.synchronize()
+    assert np.array_equal(acc.cpu().numpy().astype(np.float64), a_default)
+    g0 = torch.ones((w.n, 3), dtype=torch.float32, device=cuda)
+    gpos0 = hsr.force_vjp(pos, mass, w.box, w.r_cut, w.eps, w.poly, g0)
+    torch.cuda.synchronize()
+    assert np.array_equal(gpos.cpu().numpy(), gpos0.cpu().numpy())
+
+
 def test_reproducible_and_integer_cell_translation(cuda):
     # r_cut = 3/192 = 1/64 gives 64 chaining cells of exact side 2^-6: an
     # integer-cell shift in x and y leaves every cell-relative coordinate and
