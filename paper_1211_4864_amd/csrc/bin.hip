@@ -1,10 +1,12 @@
 // Chaining-mesh binning: cell keys and cell-relative float32 records,
-// stable LSD radix passes, the occupancy histogram of the sorted keys (wave-
-// aggregated atomics: sorted keys arrive in runs), its exclusive prefix scan
-// (cell_start), and the gather of the records into sorted order.  The sort key is the cell index followed by the Morton code of the
-// particle's sub-cell (4^3 per cell when the key has room), so a cell's
-// particles are grouped spatially and, within a sub-cell, keep their input
-// order: the binning is deterministic.
+// stable LSD radix passes (each block orders its tile of keys in LDS and
+// writes each digit's keys out as one run), the occupancy histogram of the
+// sorted keys (wave-aggregated atomics: sorted keys arrive in runs), its
+// exclusive prefix scan (cell_start), and the gather of the records into
+// sorted order.  The sort key is the cell index followed by the Morton code
+// of the particle's sub-cell (4^3 per cell when the key has room), so a
+// cell's particles are grouped spatially and, within a sub-cell, keep their
+// input order: the binning is deterministic.
 //
 // The chaining mesh is the cell list of the particle-particle part of a
 // P^3M code (Habib et al. 2012, Sec. II); cells are at least r_cut wide so
@@ -209,7 +211,10 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(
 }
 
 // ---------------------------------------------------------------- radix
-// One stable counting-sort pass on a DB-bit digit of the sort key.
+// One stable counting-sort pass on a DB-bit digit of the sort key: per
+// block digit histograms, their scan (digit-major over the blocks), then the
+// scatter.  This direct scatter writes each element as it is ranked; it
+// serves digits of 11 bits, whose LDS-staged variant below would not fit.
 
 template <int DB>
 __global__ __launch_bounds__(kBlock) void k_radix_hist(
