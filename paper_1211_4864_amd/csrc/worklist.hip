@@ -90,9 +90,9 @@ __device__ int window_sources(int key, const int* cs, const Geom& g) {
             for (int c = -1; c <= 1; ++c) {
                 int x = cx + a, y = cy + b, z = cz + c;
                 if (g.periodic) {
-                    x = (x + N) % N;
-                    y = (y + N) % N;
-                    z = (z + N) % N;
+                    x = x < 0 ? x + N : (x >= N ? x - N : x);
+                    y = y < 0 ? y + N : (y >= N ? y - N : y);
+                    z = z < 0 ? z + N : (z >= N ? z - N : z);
                 } else if (x < 0 || x >= N || y < 0 || y >= N || z < 0 || z >= N) {
                     continue;
                 }
