@@ -268,7 +268,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(
         const int rank = __popcll(pm & lanemask_lt());
         if (active && rank == 0) wcnt[w][d] = __popcll(pm);
         __syncthreads();
-        // each digit: exclusive prefix over the waves of this round
+        // each digit: exclusive prefix over the waves for these 256 keys
         for (int t = threadIdx.x; t < R; t += kBlock) {
             int acc = run_d[t];
 #pragma unroll
