@@ -95,3 +95,66 @@ def potential(pos, mass, box, r_cut, eps, poly):
     mm = mass[iu[0]] * mass[iu[1]]
     keep = s < rc2
     return float(np.sum(mm[keep] * (psi(s[keep]) - psi(rc2))))
+
+
+def newton_magnitude(pos, mass, box, r_cut, eps, targets=None, chunk=256):
+    """A_i = sum_{j != i, s < r_cut^2} m_j (s + eps)^(-3/2) |d_ij|: the summed
+    magnitude of the Newtonian parts of the pair forces of Eq. 7 on particle
+    i, before the grid polynomial cancels any of it (the scale that floors
+    relative force errors)."""
+    pos = np.asarray(pos, dtype=np.float64)
+    mass = np.asarray(mass, dtype=np.float32).astype(np.float64)
+    rc2 = float(np.float32(r_cut)) ** 2
+    e = float(np.float32(eps))
+    n = pos.shape[0]
+    idx_all = np.arange(n) if targets is None else np.asarray(targets)
+    out = np.zeros(idx_all.size)
+    for s0 in range(0, idx_all.size, chunk):
+        idx = idx_all[s0:s0 + chunk]
+        d = _pairs(pos, box, idx)
+        s = np.einsum("ijk,ijk->ij", d, d)
+        keep = (s < rc2) & (np.arange(n)[None, :] != idx[:, None])
+        r = np.sqrt(s)
+        out[s0:s0 + idx.size] = np.where(keep, mass[None, :] * r * (s + e) ** -1.5,
+                                         0.0).sum(axis=1)
+    return out
+
+
+def vjp_floors(pos, mass, box, r_cut, eps, poly, g, targets=None, chunk=256):
+    """The two magnitudes that floor relative VJP errors, per target k, over
+    its in-cut-off pairs (w = m_k g_j - m_j g_k, N = (s + eps)^(-3/2),
+    p the grid polynomial):
+
+    B_k = sum_j (N + |p| + 2 s (1.5 N / (s + eps) + |p'|)) |w|, the parts of
+          f and f' before the polynomial cancels the Newtonian term;
+    P_k = sum_j (|f| + 2 |f'| s) |w|, the parts f w and 2 f' (d.w) d of the
+          pair term with |d.w| bounded by |d||w|.
+    """
+    pos = np.asarray(pos, dtype=np.float64)
+    mass = np.asarray(mass, dtype=np.float32).astype(np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    c = np.asarray(poly, dtype=np.float32).astype(np.float64)
+    dc = P.polyder(c)
+    rc2 = float(np.float32(r_cut)) ** 2
+    e = float(np.float32(eps))
+    n = pos.shape[0]
+    idx_all = np.arange(n) if targets is None else np.asarray(targets)
+    b_out = np.zeros(idx_all.size)
+    p_out = np.zeros(idx_all.size)
+    for s0 in range(0, idx_all.size, chunk):
+        idx = idx_all[s0:s0 + chunk]
+        d = _pairs(pos, box, idx)
+        s = np.einsum("ijk,ijk->ij", d, d)
+        keep = (s < rc2) & (np.arange(n)[None, :] != idx[:, None])
+        newt = (s + e) ** -1.5
+        pv = P.polyval(s, c)
+        dpv = P.polyval(s, dc)
+        f = newt - pv
+        fp = -1.5 * newt / (s + e) - dpv
+        w = mass[idx][:, None, None] * g[None, :, :] - mass[None, :, None] * g[idx][:, None, :]
+        wn = np.sqrt(np.einsum("ijk,ijk->ij", w, w))
+        bterm = (newt + np.abs(pv) + 2.0 * s * (1.5 * newt / (s + e) + np.abs(dpv))) * wn
+        pterm = (np.abs(f) + 2.0 * np.abs(fp) * s) * wn
+        b_out[s0:s0 + idx.size] = np.where(keep, bterm, 0.0).sum(axis=1)
+        p_out[s0:s0 + idx.size] = np.where(keep, pterm, 0.0).sum(axis=1)
+    return b_out, p_out

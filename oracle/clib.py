@@ -43,7 +43,7 @@ def _load():
         lib.oracle_force.restype = ctypes.c_int
         lib.oracle_force_vjp.argtypes = [P, P, I64, ctypes.c_double,
                                          ctypes.c_float, ctypes.c_float, P, P,
-                                         P, I64, P, P, ctypes.c_double, P]
+                                         P, I64, P, P, P, ctypes.c_double, P]
         lib.oracle_force_vjp.restype = ctypes.c_int
         lib.oracle_num_threads.restype = ctypes.c_int
         _lib = lib
@@ -88,31 +88,39 @@ def force(pos, mass, box, r_cut, eps, poly, targets=None):
     return acc, an, cnt
 
 
-def force_vjp(pos, mass, box, r_cut, eps, poly, g, targets=None, cut_band=None):
+def force_vjp(pos, mass, box, r_cut, eps, poly, g, targets=None, cut_band=None,
+              pair_floor=False):
     """dL/dx (nt,3) for L = sum g . a, and the error floor B (nt,): the summed
     magnitudes of the Newtonian and grid-polynomial parts of f and f' times
     |w| over the particle's pairs.
 
     With ``cut_band`` also returns the summed pair-term magnitude of pairs
     within a relative band |s - r_cut^2| <= cut_band r_cut^2 (nt,): the
-    result is discontinuous there, since f' jumps at the cut-off."""
+    result is discontinuous there, since f' jumps at the cut-off.
+
+    With ``pair_floor`` also returns (last) the tighter floor
+    sum_j (|f| + 2 |f'| s) |w_kj| over the in-cut-off pairs (nt,)."""
     pos, mass, poly, targets = _prep(pos, mass, poly, targets)
     g = np.ascontiguousarray(g, dtype=np.float64)
     assert g.shape == pos.shape
     nt = pos.shape[0] if targets is None else targets.size
     out = np.zeros((nt, 3))
     bn = np.zeros(nt)
+    pm = np.zeros(nt)
     amb = np.zeros(nt)
     rc = _load().oracle_force_vjp(_ptr(pos), _ptr(mass), pos.shape[0],
                                   float(box), float(r_cut), float(eps),
                                   _ptr(poly), _ptr(g), _ptr(targets), nt,
-                                  _ptr(out), _ptr(bn),
+                                  _ptr(out), _ptr(bn), _ptr(pm),
                                   float(cut_band or 0.0), _ptr(amb))
     if rc != 0:
         raise MemoryError("oracle_force_vjp failed")
+    res = [out, bn]
     if cut_band is not None:
-        return out, bn, amb
-    return out, bn
+        res.append(amb)
+    if pair_floor:
+        res.append(pm)
+    return tuple(res)
 
 
 def rel_err_floored(approx, exact, floor_mag, floor_frac=0.1):

@@ -235,6 +235,10 @@ int oracle_force(const double *pos, const float *mass, int64_t n, double box,
  * Newtonian term, the scale used to floor relative errors (the analogue for
  * the VJP of the Newtonian magnitude that floors force errors).
  *
+ * pmag (may be NULL): (nt,) sum_j (|f| + 2 |f'| s) |w_kj| over the in-cut-off
+ * pairs, the summed magnitudes of the pair terms' two parts f w and
+ * 2 f' (d.w) d bounded through |d.w| <= |d||w| (a second, tighter floor).
+ *
  * f' jumps at the cut-off (f itself is continuous there), so the VJP is
  * discontinuous wherever a pair sits on r_cut: an implementation that takes
  * the cut-off test in a lower precision may count such a pair on the other
@@ -245,8 +249,8 @@ int oracle_force(const double *pos, const float *mass, int64_t n, double box,
 int oracle_force_vjp(const double *pos, const float *mass, int64_t n,
                      double box, float r_cut, float eps, const float poly[6],
                      const double *gvec, const int64_t *targets, int64_t nt,
-                     double *out, double *bnorm, double cut_band,
-                     double *amb) {
+                     double *out, double *bnorm, double *pmag,
+                     double cut_band, double *amb) {
     cellgrid g;
     double c[6];
     for (int k = 0; k < 6; ++k) c[k] = (double)poly[k];
@@ -256,7 +260,7 @@ int oracle_force_vjp(const double *pos, const float *mass, int64_t n,
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t t = 0; t < nt; ++t) {
         const int64_t k = targets ? targets[t] : t;
-        double o[3] = {0.0, 0.0, 0.0}, b = 0.0, am = 0.0;
+        double o[3] = {0.0, 0.0, 0.0}, b = 0.0, pm = 0.0, am = 0.0;
         const double mk = (double)mass[k];
         const double gk[3] = {gvec[3 * k], gvec[3 * k + 1], gvec[3 * k + 2]};
         int64_t cells[27];
@@ -286,6 +290,7 @@ int oracle_force_vjp(const double *pos, const float *mass, int64_t n,
                 if (s < rc2) {
                     for (int r = 0; r < 3; ++r) o[r] += f * w[r] + 2.0 * fp * dw * d[r];
                     b += (newt + fabs(pv) + 2.0 * s * (1.5 * newt / se + fabs(dpv))) * wn;
+                    pm += mag;
                 }
             }
         }
@@ -293,6 +298,7 @@ int oracle_force_vjp(const double *pos, const float *mass, int64_t n,
         out[3 * t + 1] = o[1];
         out[3 * t + 2] = o[2];
         if (bnorm) bnorm[t] = b;
+        if (pmag) pmag[t] = pm;
         if (amb) amb[t] = am;
     }
     free_grid(&g);
