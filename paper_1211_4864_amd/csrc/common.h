@@ -46,10 +46,7 @@ struct WorkItem {
 // Small cells are merged into runs of up to kZRun cells along z (one item,
 // one source window of 3 x 3 x (zlen + 2) cells) when a whole aligned block
 // holds at most kItemI targets.
-#ifndef HSR_ZRUN
-#define HSR_ZRUN 2
-#endif
-constexpr int kZRun = HSR_ZRUN;
+constexpr int kZRun = 2;
 constexpr int kMaxSegments = 9 * (kZRun + 2);   // stencil cells of a run
 
 constexpr int kItemI = 64;     // lanes of a wave
@@ -117,6 +114,13 @@ hipError_t launch_vjp_plain(const float4* rec, const float4* gsorted,
                             const int* keys_sorted, const int* cell_start,
                             const int* perm, int n, Geom g, PairParams p,
                             double* out, hipStream_t st);
+
+// float32 VALU rate probes (probe.hip), measurement only
+size_t probe_scratch_bytes();
+size_t probe_clock_offset();
+int probe_ops_per_iter(int kind);
+hipError_t launch_valu_probe(int kind, int waves, int iters, void* scratch,
+                             hipStream_t st);
 
 // kick / stream (integrate.hip)
 hipError_t launch_kick(double* vel, const float* acc, int64_t m, double dt,

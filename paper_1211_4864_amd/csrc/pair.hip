@@ -19,10 +19,9 @@
 // Arithmetic: pair terms in float32 on item-frame coordinates (within 1.5
 // cell sides of the item's centre, 2 for a run, so differences of close
 // pairs keep their bits); the cut-off is a branch around the pair term;
-// each lane
-// accumulates 32 sources in plain float32 and merges them into a
-// Kahan-compensated float32 sum; the k lanes of a target are combined in
-// float64.  The grid-force polynomial is evaluated by Horner in
+// each lane accumulates 32 sources in plain float32 and merges them into a
+// Kahan-compensated float32 sum; the k lanes of a target are combined with
+// float32 two-sums.  No float64 arithmetic.  The grid-force polynomial is evaluated by Horner in
 // t = alpha (s + eps) + beta, in [-1, 1] over the cut-off range, whose
 // coefficients the host derives in float64 from the caller's s-basis ones.
 // The library is compiled without floating-point contraction; every fused
@@ -33,43 +32,17 @@ namespace hsr {
 
 namespace {
 
-// Tuning knobs (build-time): sources per round, unroll, merge interval,
-// whether the next round is loaded into registers during the current one,
-// and the minimum number of waves per SIMD the register allocation must
-// allow.  The defaults are the fastest measured on MI355X for the 256^3
-// clustered workload: high occupancy hides the staging latency better than
-// register prefetch.
-#ifndef HSR_TILE
-#define HSR_TILE 256
-#endif
-#ifndef HSR_UNROLL
-#define HSR_UNROLL 2
-#endif
-#ifndef HSR_MERGE
-#define HSR_MERGE 32
-#endif
-#ifndef HSR_MIN_WAVES
-#define HSR_MIN_WAVES 8
-#endif
-#ifndef HSR_PREFETCH
-#define HSR_PREFETCH 0
-#endif
-#ifndef HSR_VJP_TILE
-#define HSR_VJP_TILE 128
-#endif
-#ifndef HSR_VJP_MIN_WAVES
-#define HSR_VJP_MIN_WAVES 6
-#endif
-#ifndef HSR_VJP_UNROLL
-#define HSR_VJP_UNROLL 2
-#endif
-#ifndef HSR_VJP_PREFETCH
-#define HSR_VJP_PREFETCH 0
-#endif
-
-constexpr int kT = HSR_TILE;       // sources per LDS tile
-constexpr int kU = HSR_UNROLL;     // sources per lane per unrolled step
-constexpr int kMerge = HSR_MERGE;  // sources per lane between compensated merges
+// Launch shape and loop structure, the fastest measured on MI355X for the
+// 256^3 clustered workload: high occupancy hides the staging latency, and
+// the LDS reads of an unrolled step are issued together before its cut-off
+// branches, so that a wave waits on LDS once per step rather than per pair.
+constexpr int kT = 256;            // sources per LDS tile (forward)
+constexpr int kU = 2;              // sources per lane per unrolled step
+constexpr int kMerge = 32;         // sources per lane between compensated merges
+constexpr int kMinWaves = 8;       // forward: waves per SIMD the registers allow
+constexpr int kVT = 128;           // sources per LDS tile (VJP)
+constexpr int kVU = 2;             // VJP sources per lane per unrolled step
+constexpr int kVMinWaves = 6;      // VJP: waves per SIMD the registers allow
 constexpr int kSeg = 64;           // segment table entries (stencil cells of a run)
 static_assert(kMaxSegments <= kSeg, "a run's stencil must fit the segment table");
 
@@ -93,34 +66,18 @@ __device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
     s = t;
 }
 
-#ifndef HSR_VCONST
-#define HSR_VCONST 1
-#endif
-// Cut-off as a branch instead of a select.  The compiler moves the whole
-// pair term under an exec mask, which it skips when the source is out of
-// range for every target of the wave.  That skip is rare (the instruction
-// counters show one reciprocal square root per candidate pair-wave); the
-// measured gain, 7% forward and 12% VJP, comes from the selects it removes.
-// Bitwise the same results as the select.
-#ifndef HSR_BRANCH_CUT
-#define HSR_BRANCH_CUT 1
-#endif
-// LDS reads of a step's sources issued together before any of its cut-off
-// branches (1), and also one step ahead (2), so that a wave does not wait on
-// LDS latency once per pair.
-#ifndef HSR_LDS_PIPE
-#define HSR_LDS_PIPE 1
-#endif
-#ifndef HSR_VJP_LDS_PIPE
-#define HSR_VJP_LDS_PIPE 1
-#endif
+// The cut-off is a branch around the pair term rather than a select: the
+// compiler moves the whole term under the test's exec mask, which the wave
+// skips when a source is out of range for all its targets.  That skip is
+// rare (the instruction counters show one reciprocal square root per
+// candidate pair-wave); the measured gain, 7% forward and 12% VJP, comes
+// from the selects the branch removes.  Bitwise the same results.
 
 // Copy of a wave-uniform constant held in a vector register.  A VALU
 // instruction reads at most one scalar register, so an FMA of two scalar
 // constants needs one of them in a vector register; the compiler would
 // otherwise copy it there again on every loop iteration.
 __device__ __forceinline__ float in_vgpr(float s) {
-    if (!HSR_VCONST) return s;
     float v;
     asm("v_mov_b32 %0, %1" : "=v"(v) : "s"(s));
     return v;
@@ -134,11 +91,21 @@ __device__ __forceinline__ float4 uniform(float4 v) {
     return make_float4(uniform(v.x), uniform(v.y), uniform(v.z), uniform(v.w));
 }
 
-// Sum over the k lanes of each target (lanes t*k .. t*k + k - 1), k a power
-// of two; every lane of the group ends with the group total.
-__device__ __forceinline__ double group_sum(double v, int k) {
-    for (int o = 1; o < k; o <<= 1) v += __shfl_xor(v, o);
-    return v;
+// Combines the compensated sums (s, c) of the k lanes of each target (lanes
+// t*k .. t*k + k - 1, k a power of two) in float32: the exact rounding error
+// of each pairwise sum (Knuth's two-sum) joins the compensation terms.
+// Every lane of the group ends with the group's value s - c.
+__device__ __forceinline__ float group_sum(float s, float c, int k) {
+    for (int o = 1; o < k; o <<= 1) {
+        const float s2 = __shfl_xor(s, o);
+        const float c2 = __shfl_xor(c, o);
+        const float t = s + s2;
+        const float bb = t - s;
+        const float e = (s - (t - bb)) + (s2 - bb);   // s + s2 = t + e exactly
+        s = t;
+        c = (c + c2) - e;
+    }
+    return s - c;
 }
 
 // Coordinate relative to its own cell's lower corner, shifted by `cells`
@@ -230,8 +197,6 @@ __device__ __forceinline__ float4 shift_into_frame(float4 r, int code, float Lc,
                        frame(r.z, (float)((code >> 16) & 255) - (1.0f + zc), Lc), r.w);
 }
 
-constexpr int kVT = HSR_VJP_TILE;     // sources per LDS tile of the VJP kernel
-constexpr int kVU = HSR_VJP_UNROLL;   // VJP sources per lane per unrolled step
 static_assert(kVT % (kItemI * kVU) == 0, "VJP tile must hold whole steps");
 
 // Segment holding window position p (0 <= p < total): the last q with
@@ -411,49 +376,30 @@ __device__ __forceinline__ void force_tile(const float4* __restrict__ src,
     for (int j0 = 0; j0 < nit; j0 += kMerge) {
         float tx = 0.f, ty = 0.f, tz = 0.f;
         const int lim = min(j0 + kMerge, nit);
-        float4 nxt[kU];
-        if (HSR_LDS_PIPE >= 2) {
-#pragma unroll
-            for (int u = 0; u < kU; ++u) nxt[u] = src[(j0 + u) * st];
-        }
         for (int jj = j0; jj < lim; jj += kU) {
             float4 cur[kU];
 #pragma unroll
-            for (int u = 0; u < kU; ++u)
-                cur[u] = HSR_LDS_PIPE >= 2 ? nxt[u]
-                                           : (HSR_LDS_PIPE ? src[(jj + u) * st]
-                                                           : float4{});
-            if (HSR_LDS_PIPE >= 2 && jj + kU < lim) {
-#pragma unroll
-                for (int u = 0; u < kU; ++u) nxt[u] = src[(jj + kU + u) * st];
-            }
+            for (int u = 0; u < kU; ++u) cur[u] = src[(jj + u) * st];
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
-                const float4 pj = HSR_LDS_PIPE ? cur[u] : src[(jj + u) * st];
+                const float4 pj = cur[u];
                 const float dx = pj.x - xi.x;
                 const float dy = pj.y - xi.y;
                 const float dz = pj.z - xi.z;
                 float sp = __builtin_fmaf(dx, dx, c.eps);
                 sp = __builtin_fmaf(dy, dy, sp);
                 sp = __builtin_fmaf(dz, dz, sp);
-                const float y = __builtin_amdgcn_rsqf(sp);
-                const float t = __builtin_fmaf(sp, alpha, c.beta);
-                float p = __builtin_fmaf(b5, t, c.b4);
-                p = __builtin_fmaf(p, t, c.b3);
-                p = __builtin_fmaf(p, t, c.b2);
-                p = __builtin_fmaf(p, t, c.b1);
-                p = __builtin_fmaf(p, t, c.b0);
-                const float y2 = y * y;
-                const float f = __builtin_fmaf(y2, y, -p);
-                if (HSR_BRANCH_CUT) {
-                    if (sp < c.rc2e) {
-                        const float mf = UNI ? f : pj.w * f;
-                        tx = __builtin_fmaf(mf, dx, tx);
-                        ty = __builtin_fmaf(mf, dy, ty);
-                        tz = __builtin_fmaf(mf, dz, tz);
-                    }
-                } else {
-                    const float mf = sp < c.rc2e ? (UNI ? f : pj.w * f) : 0.0f;
+                if (sp < c.rc2e) {
+                    const float y = __builtin_amdgcn_rsqf(sp);
+                    const float t = __builtin_fmaf(sp, alpha, c.beta);
+                    float p = __builtin_fmaf(b5, t, c.b4);
+                    p = __builtin_fmaf(p, t, c.b3);
+                    p = __builtin_fmaf(p, t, c.b2);
+                    p = __builtin_fmaf(p, t, c.b1);
+                    p = __builtin_fmaf(p, t, c.b0);
+                    const float y2 = y * y;
+                    const float f = __builtin_fmaf(y2, y, -p);
+                    const float mf = UNI ? f : pj.w * f;
                     tx = __builtin_fmaf(mf, dx, tx);
                     ty = __builtin_fmaf(mf, dy, ty);
                     tz = __builtin_fmaf(mf, dz, tz);
@@ -471,7 +417,7 @@ __device__ __forceinline__ void force_tile(const float4* __restrict__ src,
     }
 }
 
-__global__ __launch_bounds__(kWave, HSR_MIN_WAVES) void k_pair_force(
+__global__ __launch_bounds__(kWave, kMinWaves) void k_pair_force(
     const WorkItem* __restrict__ items, const int* __restrict__ n_items_dev,
     const float4* __restrict__ rec, const int* __restrict__ cs,
     const int* __restrict__ perm, Geom g, PairParams P,
@@ -501,21 +447,16 @@ __global__ __launch_bounds__(kWave, HSR_MIN_WAVES) void k_pair_force(
     float s[3] = {0.f, 0.f, 0.f}, cc[3] = {0.f, 0.f, 0.f};
 
     Round<false, kT> R;
-    int seg = 0;
-    if (HSR_PREFETCH && total > 0) load_round(sg, segoff, 0, 0, total, rec, rec, R);
     for (int cursor = 0; cursor < total; cursor += kT) {
         bool mixed;
-        seg = segment_of(segoff, cursor);
-        if (!HSR_PREFETCH) load_round(sg, segoff, seg, cursor, total, rec, rec, R);
+        const int seg = segment_of(segoff, cursor);
+        load_round(sg, segoff, seg, cursor, total, rec, rec, R);
         const int cnt = compact_round(R, lo, hi, P.cull2, Lc, 0.5f * it.zlen, mref,
                                       tile, tile,
                                       nullptr, &mixed);
         const int cntp = padded_count(cnt, L.ks);
         for (int q = cnt + lane; q < cntp; q += kWave) tile[q] = pad;
         __syncthreads();
-        if (HSR_PREFETCH && cursor + kT < total)
-            load_round(sg, segoff, segment_of(segoff, cursor + kT), cursor + kT,
-                       total, rec, rec, R);
         const int nit = cntp / L.ks;          // sources per lane in this tile
         const float4* src = tile + L.r;
         const bool uni = targets_equal && !mixed;
@@ -528,14 +469,14 @@ __global__ __launch_bounds__(kWave, HSR_MIN_WAVES) void k_pair_force(
         }
         __syncthreads();
     }
-    const double ax = group_sum((double)s[0] - (double)cc[0], L.ks);
-    const double ay = group_sum((double)s[1] - (double)cc[1], L.ks);
-    const double az = group_sum((double)s[2] - (double)cc[2], L.ks);
+    const float ax = group_sum(s[0], cc[0], L.ks);
+    const float ay = group_sum(s[1], cc[1], L.ks);
+    const float az = group_sum(s[2], cc[2], L.ks);
     if (L.ki >= 0 && L.r == 0) {
         const int64_t o = 3 * (int64_t)dst;
-        out_acc[o] = (float)ax;
-        out_acc[o + 1] = (float)ay;
-        out_acc[o + 2] = (float)az;
+        out_acc[o] = ax;
+        out_acc[o + 1] = ay;
+        out_acc[o + 2] = az;
     }
 }
 
@@ -565,9 +506,8 @@ __global__ __launch_bounds__(kWave) void k_pair_count(
     unsigned long long inside = 0;
     int kept = 0;
     Round<false, kT> R;
-    int seg = 0;
     for (int cursor = 0; cursor < total; cursor += kT) {
-        seg = segment_of(segoff, cursor);
+        const int seg = segment_of(segoff, cursor);
         load_round(sg, segoff, seg, cursor, total, rec, rec, R);
         bool mixed;
         const int cnt = compact_round(R, lo, hi, P.cull2, Lc, 0.5f * it.zlen, 0.0f,
@@ -623,77 +563,63 @@ __device__ __forceinline__ void vjp_tile(const float4* __restrict__ srcA,
     for (int j0 = 0; j0 < nit; j0 += kMerge) {
         float tx = 0.f, ty = 0.f, tz = 0.f;
         const int lim = min(j0 + kMerge, nit);
-        float4 nxa[kVU], nxb[kVU];
-        if (HSR_VJP_LDS_PIPE >= 2) {
-#pragma unroll
-            for (int u = 0; u < kVU; ++u) {
-                nxa[u] = srcA[(j0 + u) * st];
-                nxb[u] = srcB[(j0 + u) * st];
-            }
-        }
         for (int jj = j0; jj < lim; jj += kVU) {
             float4 ca[kVU], cb[kVU];
 #pragma unroll
             for (int u = 0; u < kVU; ++u) {
-                ca[u] = HSR_VJP_LDS_PIPE >= 2 ? nxa[u] : (HSR_VJP_LDS_PIPE ? srcA[(jj + u) * st] : float4{});
-                cb[u] = HSR_VJP_LDS_PIPE >= 2 ? nxb[u] : (HSR_VJP_LDS_PIPE ? srcB[(jj + u) * st] : float4{});
-            }
-            if (HSR_VJP_LDS_PIPE >= 2 && jj + kVU < lim) {
-#pragma unroll
-                for (int u = 0; u < kVU; ++u) {
-                    nxa[u] = srcA[(jj + kVU + u) * st];
-                    nxb[u] = srcB[(jj + kVU + u) * st];
-                }
+                ca[u] = srcA[(jj + u) * st];
+                cb[u] = srcB[(jj + u) * st];
             }
 #pragma unroll
             for (int u = 0; u < kVU; ++u) {
-                const float4 pj = HSR_VJP_LDS_PIPE ? ca[u] : srcA[(jj + u) * st];
-                const float4 gj = HSR_VJP_LDS_PIPE ? cb[u] : srcB[(jj + u) * st];
+                const float4 pj = ca[u];
+                const float4 gj = cb[u];
                 const float dx = pj.x - xk.x;
                 const float dy = pj.y - xk.y;
                 const float dz = pj.z - xk.z;
                 float sp = __builtin_fmaf(dx, dx, c.eps);
                 sp = __builtin_fmaf(dy, dy, sp);
                 sp = __builtin_fmaf(dz, dz, sp);
-                const float y = __builtin_amdgcn_rsqf(sp);
-                const float t = __builtin_fmaf(sp, alpha, c.beta);
-                float p = __builtin_fmaf(b5, t, c.b4);
-                p = __builtin_fmaf(p, t, c.b3);
-                p = __builtin_fmaf(p, t, c.b2);
-                p = __builtin_fmaf(p, t, c.b1);
-                p = __builtin_fmaf(p, t, c.b0);
-                float q = __builtin_fmaf(q4, t, v.q3);
-                q = __builtin_fmaf(q, t, v.q2);
-                q = __builtin_fmaf(q, t, v.q1);
-                q = __builtin_fmaf(q, t, v.q0);
-                const float y2 = y * y;
-                const float y3 = y2 * y;
-                const float y5 = y3 * y2;
-                const bool in = sp < c.rc2e;
-                if (HSR_BRANCH_CUT && !in) continue;
-                const float f = (HSR_BRANCH_CUT || in) ? y3 - p : 0.0f;
-                const float f2 =
-                    (HSR_BRANCH_CUT || in) ? __builtin_fmaf(-3.0f, y5, -q) : 0.0f;
-                float wx, wy, wz;
-                if (UNI) {
-                    wx = gj.x - gk.x;
-                    wy = gj.y - gk.y;
-                    wz = gj.z - gk.z;
-                } else {
-                    wx = __builtin_fmaf(mk, gj.x, -(pj.w * gk.x));
-                    wy = __builtin_fmaf(mk, gj.y, -(pj.w * gk.y));
-                    wz = __builtin_fmaf(mk, gj.z, -(pj.w * gk.z));
+                if (sp < c.rc2e) {
+                    const float y = __builtin_amdgcn_rsqf(sp);
+                    const float t = __builtin_fmaf(sp, alpha, c.beta);
+                    float p = __builtin_fmaf(b5, t, c.b4);
+                    p = __builtin_fmaf(p, t, c.b3);
+                    p = __builtin_fmaf(p, t, c.b2);
+                    p = __builtin_fmaf(p, t, c.b1);
+                    p = __builtin_fmaf(p, t, c.b0);
+                    float q = __builtin_fmaf(q4, t, v.q3);
+                    q = __builtin_fmaf(q, t, v.q2);
+                    q = __builtin_fmaf(q, t, v.q1);
+                    q = __builtin_fmaf(q, t, v.q0);
+                    const float y2 = y * y;
+                    const float y3 = y2 * y;
+                    const float y5 = y3 * y2;
+                    const float f = y3 - p;
+                    const float f2 = __builtin_fmaf(-3.0f, y5, -q);
+                    float wx, wy, wz;
+                    if (UNI) {
+                        wx = gj.x - gk.x;
+                        wy = gj.y - gk.y;
+                        wz = gj.z - gk.z;
+                    } else {
+                        // two separately rounded products, so that the self
+                        // pair (j = k) gives w = 0 exactly
+                        wx = mk * gj.x - pj.w * gk.x;
+                        wy = mk * gj.y - pj.w * gk.y;
+                        wz = mk * gj.z - pj.w * gk.z;
+                    }
+                    float dw = dx * wx;
+                    dw = __builtin_fmaf(dy, wy, dw);
+                    dw = __builtin_fmaf(dz, wz, dw);
+                    const float cd = f2 * dw;
+                    tx = __builtin_fmaf(f, wx, tx);
+                    ty = __builtin_fmaf(f, wy, ty);
+                    tz = __builtin_fmaf(f, wz, tz);
+                    tx = __builtin_fmaf(cd, dx, tx);
+                    ty = __builtin_fmaf(cd, dy, ty);
+                    tz = __builtin_fmaf(cd, dz, tz);
                 }
-                float dw = dx * wx;
-                dw = __builtin_fmaf(dy, wy, dw);
-                dw = __builtin_fmaf(dz, wz, dw);
-                const float cd = f2 * dw;
-                tx = __builtin_fmaf(f, wx, tx);
-                ty = __builtin_fmaf(f, wy, ty);
-                tz = __builtin_fmaf(f, wz, tz);
-                tx = __builtin_fmaf(cd, dx, tx);
-                ty = __builtin_fmaf(cd, dy, ty);
-                tz = __builtin_fmaf(cd, dz, tz);
             }
         }
         if (UNI) {
@@ -709,7 +635,7 @@ __device__ __forceinline__ void vjp_tile(const float4* __restrict__ srcA,
 
 // dL/dx_k = sum_j [f w + 2 f'(s) (d.w) d],  w = m_k g_j - m_j g_k,
 // the transpose of the Jacobian of the pair term applied to the cotangents.
-__global__ __launch_bounds__(kWave, HSR_VJP_MIN_WAVES) void k_pair_vjp(
+__global__ __launch_bounds__(kWave, kVMinWaves) void k_pair_vjp(
     const WorkItem* __restrict__ items, const int* __restrict__ n_items_dev,
     const float4* __restrict__ rec, const float4* __restrict__ gsorted,
     const int* __restrict__ cs, const int* __restrict__ perm, Geom g,
@@ -742,12 +668,10 @@ __global__ __launch_bounds__(kWave, HSR_VJP_MIN_WAVES) void k_pair_vjp(
     float s[3] = {0.f, 0.f, 0.f}, cc[3] = {0.f, 0.f, 0.f};
 
     Round<true, kVT> R;
-    int seg = 0;
-    if (HSR_VJP_PREFETCH && total > 0) load_round(sg, segoff, 0, 0, total, rec, gsorted, R);
     for (int cursor = 0; cursor < total; cursor += kVT) {
         bool mixed;
-        seg = segment_of(segoff, cursor);
-        if (!HSR_VJP_PREFETCH) load_round(sg, segoff, seg, cursor, total, rec, gsorted, R);
+        const int seg = segment_of(segoff, cursor);
+        load_round(sg, segoff, seg, cursor, total, rec, gsorted, R);
         const int cnt = compact_round(R, lo, hi, P.cull2, Lc, 0.5f * it.zlen, mref,
                                       tileA, tileB,
                                       nullptr, &mixed);
@@ -757,9 +681,6 @@ __global__ __launch_bounds__(kWave, HSR_VJP_MIN_WAVES) void k_pair_vjp(
             tileB[q] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
         __syncthreads();
-        if (HSR_VJP_PREFETCH && cursor + kVT < total)
-            load_round(sg, segoff, segment_of(segoff, cursor + kVT), cursor + kVT,
-                       total, rec, gsorted, R);
         const int nit = cntp / L.ks;
         const float4* srcA = tileA + L.r;
         const float4* srcB = tileB + L.r;
@@ -773,14 +694,15 @@ __global__ __launch_bounds__(kWave, HSR_VJP_MIN_WAVES) void k_pair_vjp(
         }
         __syncthreads();
     }
-    const double gx = group_sum((double)s[0] - (double)cc[0], L.ks);
-    const double gy = group_sum((double)s[1] - (double)cc[1], L.ks);
-    const double gz = group_sum((double)s[2] - (double)cc[2], L.ks);
+    const float gx = group_sum(s[0], cc[0], L.ks);
+    const float gy = group_sum(s[1], cc[1], L.ks);
+    const float gz = group_sum(s[2], cc[2], L.ks);
     if (L.ki >= 0 && L.r == 0) {
+        // float32 result stored in the float64 output (a conversion only)
         const int64_t o = 3 * (int64_t)dst;
-        out_grad[o] = gx;
-        out_grad[o + 1] = gy;
-        out_grad[o + 2] = gz;
+        out_grad[o] = (double)gx;
+        out_grad[o + 1] = (double)gy;
+        out_grad[o + 2] = (double)gz;
     }
 }
 

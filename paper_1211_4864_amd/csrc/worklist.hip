@@ -29,10 +29,6 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kXcd = kXcds;
 
-#ifndef HSR_XCD_ORDER
-#define HSR_XCD_ORDER 1
-#endif
-
 __device__ __forceinline__ int floor_pow2(int v) {
     return v <= 0 ? 0 : (1 << (31 - __clz(v)));
 }
@@ -147,7 +143,7 @@ __global__ __launch_bounds__(1024) void k_column_xcd(
         // the column goes to the XCD that holds the midpoint of its work
         const double mid = (double)run + 0.5 * (double)col_cost[q];
         int x = total ? (int)(mid * kXcd / (double)total) : 0;
-        col_xcd[q] = HSR_XCD_ORDER ? min(kXcd - 1, max(0, x)) : 0;
+        col_xcd[q] = min(kXcd - 1, max(0, x));
         run += col_cost[q];
     }
 }
