@@ -36,16 +36,40 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
+def hashed_files():
+    """Every file the library is compiled from: the HIP sources, the internal
+    header and the public header."""
+    return sorted(glob.glob(os.path.join(CSRC, "*.hip")) +
+                  glob.glob(os.path.join(CSRC, "*.h"))) + [
+        os.path.join(INCLUDE, "hacc_sr.h")]
+
+
+def source_hash() -> str:
+    """sha256 over the names and exact bytes of the files in hashed_files().
+    The build embeds it in the library (hacc_sr_source_hash), and the binding
+    refuses a library whose embedded hash differs from the sources in the
+    tree, so a stale build never runs."""
+    import hashlib
+    h = hashlib.sha256()
+    for path in hashed_files():
+        h.update(os.path.relpath(path, ROOT).encode() + b"\0")
+        with open(path, "rb") as f:
+            h.update(f.read())
+        h.update(b"\0")
+    return h.hexdigest()
+
+
 def build(verbose: bool = False, extra_flags=(), out: str = LIB) -> str:
     """Compile every csrc/*.hip into one shared library and return its path."""
     tag = os.path.splitext(os.path.basename(out))[0]
     build_dir = os.path.join(os.path.dirname(out), "_build", tag)
     os.makedirs(build_dir, exist_ok=True)
     objs = []
+    tag_flag = f'-DHSR_SOURCE_SHA256="{source_hash()}"'
     for src in sources():
         obj = os.path.join(build_dir, os.path.basename(src)[:-4] + ".o")
-        cmd = [hipcc(), *HIP_FLAGS, *extra_flags, "-I", INCLUDE, "-I", CSRC,
-               "-c", src, "-o", obj]
+        cmd = [hipcc(), *HIP_FLAGS, *extra_flags, tag_flag, "-I", INCLUDE,
+               "-I", CSRC, "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)

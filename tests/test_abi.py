@@ -118,3 +118,18 @@ def test_product_path_has_no_fallback(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError):
         _lib.load()
+
+
+def test_library_built_from_these_sources(lib):
+    from paper_1211_4864_amd import build
+    assert lib.hacc_sr_source_hash().decode() == build.source_hash()
+
+
+def test_stale_library_is_refused(lib, monkeypatch):
+    """A library whose embedded source hash differs from the sources in the
+    tree is refused at load time."""
+    from paper_1211_4864_amd import build
+    monkeypatch.setattr(build, "source_hash", lambda: "0" * 64)
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(_lib.StaleLibraryError):
+        _lib.load()
