@@ -32,6 +32,10 @@ FP32_PEAK_TFLOPS = 157.3          # MI355X FP32 vector, 256 CU x 2.4 GHz x 256 F
 FLOP_FWD = 30                     # counted FLOP per evaluated forward pair
 FLOP_VJP = 61                     # counted FLOP per evaluated adjoint pair
 WORKLOADS = {
+    "cfg1": "32^3 = 32768 particles, uniform + Gaussian displacements (0.3 cell), "
+            "periodic unit box, r_cut = 3/128, eps = 1e-5, 42^3 chaining cells, seed 1",
+    "cfg4": "cfg2 positions (128^3 = 2.1M, Plummer-clustered) with cotangents "
+            "g ~ N(0, 1) float32 for the VJP, seed 4",
     "cfg3": "256^3 = 16.8M particles, 20000 NFW halos (70%, masses log-uniform over "
             "4 decades, c 4-15) + uniform background, periodic unit box, "
             "r_cut = 3/256, eps = 2.5e-6, 85^3 chaining cells, seed 3",
@@ -109,9 +113,35 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
+def cpu_baseline_full(w, g, repeats=3):
+    """The float64 oracle over every target: forward and VJP each timed
+    `repeats` times (median).  Pair interactions per second over the two
+    passes (in-cut-off pairs, fwd + adjoint), and each pass on its own."""
+    import oracle
+    tf, tv = [], []
+    pairs = 0
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        _, _, cnt = oracle.force(w.pos, w.mass, w.box, w.r_cut, w.eps, w.poly)
+        tf.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        oracle.force_vjp(w.pos, w.mass, w.box, w.r_cut, w.eps, w.poly, g)
+        tv.append(time.perf_counter() - t0)
+        pairs = int(cnt.sum())
+    mf, mv = float(np.median(tf)), float(np.median(tv))
+    return {"value": 2.0 * pairs / (mf + mv), "unit": "pair interactions/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "fwd_interactions_per_s": pairs / mf, "adj_interactions_per_s": pairs / mv,
+            "sample": f"all {w.n} targets, float64 forward ({mf:.2f} s) and VJP "
+                      f"({mv:.2f} s), median of {repeats} runs each, {pairs} in-cut-off "
+                      f"pairs"}
+
+
 def cpu_baseline(w, sample_seconds: float, g):
     """The float64 oracle on a random sample of targets: forward and VJP.
-    Returns pair interactions per second (in-cut-off pairs, fwd + adjoint)."""
+    Returns pair interactions per second (in-cut-off pairs, fwd + adjoint),
+    the rate the whole workload would run at (extrapolated from the
+    sample)."""
     import oracle
     rng = np.random.default_rng(11)
     k = 500
@@ -134,7 +164,8 @@ def cpu_baseline(w, sample_seconds: float, g):
             "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"{k} random targets of the same workload (all their sources), "
                       f"float64 forward + VJP, {pairs} in-cut-off pairs each, "
-                      f"{elapsed:.2f} s"}
+                      f"{elapsed:.2f} s; the rate is extrapolated to the whole "
+                      f"workload"}
 
 
 def accuracy(w, acc, gradp, g):
@@ -145,25 +176,132 @@ def accuracy(w, acc, gradp, g):
     ref, an, _ = oracle.force(w.pos, w.mass, w.box, w.r_cut, w.eps, w.poly, targets=idx)
     e = oracle.rel_err_floored(acc[idx], ref, an)
     raw = np.linalg.norm(acc[idx] - ref, axis=1) / np.maximum(np.linalg.norm(ref, axis=1), 1e-300)
-    gref, bn, amb = oracle.force_vjp(w.pos, w.mass, w.box, w.r_cut, w.eps, w.poly, g,
-                                     targets=idx, cut_band=1e-6)
+    gref, bn, amb, pm = oracle.force_vjp(w.pos, w.mass, w.box, w.r_cut, w.eps, w.poly, g,
+                                         targets=idx, cut_band=1e-6, pair_floor=True)
     clean = amb == 0.0     # f' jumps at r_cut: pairs on the cut are excluded
     ge = oracle.rel_err_floored(gradp[idx][clean], gref[clean], bn[clean])
+    gp = oracle.rel_err_floored(gradp[idx][clean], gref[clean], pm[clean])
     return {"sample": int(idx.size), "force_max_err": float(e.max()),
             "force_raw_rel_median": float(np.median(raw)),
             "force_raw_rel_p99": float(np.quantile(raw, 0.99)),
+            "force_count_above_1e-5": int((e > 1e-5).sum()),
             "vjp_max_err": float(ge.max()),
+            "vjp_max_err_pair_floor": float(gp.max()),
+            "vjp_count_above_1e-4_pair_floor": int((gp > 1e-4).sum()),
             "vjp_particles_with_pairs_on_cut": int((~clean).sum()),
             "metric": "|x - x*| / max(|x*|, 0.1 F): F = summed Newtonian pair "
-                      "magnitude (forces); summed magnitude of the Newtonian and "
-                      "polynomial parts of the pair terms (VJP)"}
+                      "magnitude (forces); for the VJP, F = summed magnitude of the "
+                      "Newtonian and polynomial parts of the pair terms (vjp_max_err) "
+                      "or of the pair terms themselves, sum (|f| + 2|f'| s)|w| "
+                      "(vjp_max_err_pair_floor)"}
+
+
+def measured_peak(hsr):
+    """Float32 VALU peak measured on this GPU at the clock it sustains under
+    a VALU load: the best FMA probe rate over 1, 2, 4 and 8 waves per SIMD
+    (2 FLOP per lane operation), with the shader clock and the shader cycles
+    between two instructions of one wave, for an FMA, a reciprocal square
+    root and the forward pair term's mix (1 rsq per 18 FMA)."""
+    sweep = {w: hsr.valu_probe(hsr.PROBE_FMA, w) for w in (1, 2, 4, 8)}
+    fmac = hsr.valu_probe(hsr.PROBE_FMAC, 8)
+    best = max(sweep, key=lambda w: sweep[w]["lane_ops_per_s"])
+    top = max(sweep[best]["lane_ops_per_s"], fmac["lane_ops_per_s"])
+    rsq = hsr.valu_probe(hsr.PROBE_RSQ, 8)
+    mix = hsr.valu_probe(hsr.PROBE_PAIR_MIX, 8)
+    fma8 = sweep[8]
+    simds = 1024.0
+    clk = fma8["clock_ghz"] * 1e9
+    return {"fma_tflops": round(2.0 * top / 1e12, 3),
+            "best_waves_per_simd": best,
+            "fma_tflops_by_waves": {w: round(2.0 * r["lane_ops_per_s"] / 1e12, 3)
+                                    for w, r in sweep.items()},
+            "fmac_tflops_8_waves": round(2.0 * fmac["lane_ops_per_s"] / 1e12, 3),
+            "clock_ghz": round(fma8["clock_ghz"], 4),
+            # SIMD cycles per wave64 instruction, from the aggregate rates
+            "simd_cycles_per_fma": round(simds * 64 * clk / top, 3),
+            "simd_cycles_per_rsq": round(simds * 64 * clk / rsq["lane_ops_per_s"], 3),
+            "simd_cycles_per_mix_instr": round(simds * 64 * clk / mix["lane_ops_per_s"], 3),
+            "probe": "16 independent float32 chains per lane, one-wave workgroups, "
+                     "5 launches; packed float32 disabled"}
+
+
+def unequal_mass_leg(hsr, torch, w, pos, g_np, inside, launches=2):
+    """Both pair kernels on the same positions with masses spread over a
+    decade (m_i = 10^U(-0.5, 0.5) / N): the general path, which multiplies
+    every pair term by its mass and forms w = m_k g_j - m_j g_k from two
+    products, as the counted 30 / 61 FLOP per pair assume."""
+    dev = pos.device
+    rng = np.random.default_rng(77)
+    m = (10.0 ** rng.uniform(-0.5, 0.5, w.n) / w.n).astype(np.float32)
+    mass = torch.from_numpy(m).to(dev)
+    ga = torch.from_numpy(g_np).to(dev)
+    box, rc, eps, poly = w.box, w.r_cut, w.eps, w.poly
+    acc = hsr.force(pos, mass, box, rc, eps, poly)
+    gp = hsr.force_vjp(pos, mass, box, rc, eps, poly, ga)
+    torch.cuda.synchronize()
+    hsr.timing_enable(True)
+    for _ in range(launches):
+        hsr.force(pos, mass, box, rc, eps, poly, out=acc)
+        hsr.force_vjp(pos, mass, box, rc, eps, poly, ga, out=gp)
+    torch.cuda.synchronize()
+    n_f, ms_f = hsr.timing_read(hsr.TIMER_FORCE)
+    n_v, ms_v = hsr.timing_read(hsr.TIMER_VJP)
+    hsr.timing_enable(False)
+    f_ms, v_ms = ms_f / max(n_f, 1), ms_v / max(n_v, 1)
+    fwd = FLOP_FWD * inside / (f_ms * 1e-3) / 1e12
+    vjp = FLOP_VJP * inside / (v_ms * 1e-3) / 1e12
+    return {"force_pair_ms": round(f_ms, 4), "vjp_pair_ms": round(v_ms, 4),
+            "fwd_tflops": round(fwd, 3), "vjp_tflops": round(vjp, 3),
+            "fwd_pct_fp32_peak": round(100 * fwd / FP32_PEAK_TFLOPS, 2),
+            "vjp_pct_fp32_peak": round(100 * vjp / FP32_PEAK_TFLOPS, 2),
+            "masses": "10^U(-0.5, 0.5) / N, seed 77"}
+
+
+def rcb_leg(hsr, torch, w, pos, mass, g_np, inside, leaf_max, launches=2):
+    """The same forward and VJP with the RCB fat leaves (centre-of-mass
+    bisection inside the chaining cells) as the work items: pair-kernel
+    times, the tree build, and their roofline beside the chaining mesh's."""
+    dev = pos.device
+    ga = torch.from_numpy(g_np).to(dev)
+    box, rc, eps, poly = w.box, w.r_cut, w.eps, w.poly
+    acc = hsr.force_rcb(pos, mass, box, rc, eps, poly, leaf_max)
+    gp = hsr.force_vjp_rcb(pos, mass, box, rc, eps, poly, ga, leaf_max)
+    torch.cuda.synchronize()
+    hsr.timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(launches):
+        hsr.force_rcb(pos, mass, box, rc, eps, poly, leaf_max, out=acc)
+        hsr.force_vjp_rcb(pos, mass, box, rc, eps, poly, ga, leaf_max, out=gp)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / launches
+    n_f, ms_f = hsr.timing_read(hsr.TIMER_FORCE)
+    n_v, ms_v = hsr.timing_read(hsr.TIMER_VJP)
+    n_r, ms_r = hsr.timing_read(hsr.TIMER_RCB)
+    n_b, ms_b = hsr.timing_read(hsr.TIMER_BIN)
+    n_w, ms_w = hsr.timing_read(hsr.TIMER_WORKLIST)
+    hsr.timing_enable(False)
+    f_ms, v_ms = ms_f / max(n_f, 1), ms_v / max(n_v, 1)
+    fwd = FLOP_FWD * inside / (f_ms * 1e-3) / 1e12
+    vjp = FLOP_VJP * inside / (v_ms * 1e-3) / 1e12
+    _, _, _, ls = hsr.rcb_bin(pos, mass, box, rc, leaf_max)
+    return {"leaf_max": leaf_max, "leaves": int(ls.numel() - 1),
+            "force_pair_ms": round(f_ms, 4), "vjp_pair_ms": round(v_ms, 4),
+            "rcb_tree_ms": round(ms_r / max(n_r, 1), 4),
+            "bin_ms": round(ms_b / max(n_b, 1), 4),
+            "worklist_ms": round(ms_w / max(n_w, 1), 4),
+            "force_plus_vjp_wall_ms": round(1e3 * wall, 3),
+            "fwd_tflops": round(fwd, 3), "vjp_tflops": round(vjp, 3),
+            "fwd_pct_fp32_peak": round(100 * fwd / FP32_PEAK_TFLOPS, 2),
+            "vjp_pct_fp32_peak": round(100 * vjp / FP32_PEAK_TFLOPS, 2)}
 
 
 def plain_comparison(hsr, torch, w, pos, mass, g_np, inside, f_ms, v_ms,
                      with_accuracy, launches=2):
-    """The plain float32 kernels (one thread per target, no LDS staging, no
-    culling, Horner in the s basis, uncompensated sums) on the same input:
-    time per launch, interactions/s and accuracy on the same sample."""
+    """The plain float32 kernels (one thread per target, sources read from
+    global memory, no LDS staging, no culling; the same float32 pair formula
+    with the polynomial in the t basis; per-target sums in float64) on the
+    same input: time per launch, interactions/s and accuracy on the same
+    sample."""
     dev = pos.device
     box, rc, eps, poly = w.box, w.r_cut, w.eps, w.poly
     ga = torch.from_numpy(g_np).to(dev)
@@ -198,10 +336,19 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="cfg3", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="time the oracle over every target (median of 3) instead "
+                         "of a sample; for the small workloads cfg1, cfg2, cfg4")
+    ap.add_argument("--no-unequal", action="store_true",
+                    help="skip the unequal-mass leg")
+    ap.add_argument("--rcb", type=int, nargs="*", default=[64],
+                    help="leaf sizes of the RCB fat-leaf legs (none: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the plain float32 comparison kernels")
+    ap.add_argument("--no-probe", action="store_true",
+                    help="skip the float32 VALU rate probes (measured peak)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--rollout", type=int, default=1,
@@ -257,6 +404,11 @@ def main() -> int:
     cp = torch.empty_like(x)
 
     def step():
+        # every step starts from the generated state (positions as drawn,
+        # zero velocities), so each timed force and VJP sees the workload
+        # exactly as counted above
+        x.copy_(pos)
+        v.zero_()
         # forward subcycle with its checkpoint
         hsr.stream(x, v, 0.5 * h, box)
         cp.copy_(x)
@@ -319,6 +471,11 @@ def main() -> int:
             dst.copy_(src)
         torch.cuda.synchronize()
 
+    peak = None
+    if not args.no_probe:
+        peak = measured_peak(hsr)
+        log(f"[bench] measured VALU peak {peak}")
+
     ms_step = 1e3 * t_total / args.steps
     value = 2.0 * n_c * inside / (t_total / args.steps)
     f_ms = ms_f / max(n_f, 1)
@@ -336,6 +493,9 @@ def main() -> int:
             "traffic": measured_traffic(dom[4]),
             "flop_per_pair": dom[2], "pairs_per_launch": inside,
             "avg_launch_ms": round(dom[3], 4)}
+    if peak is not None:
+        roof["peak_measured"] = peak["fma_tflops"]
+        roof["frac_measured"] = round(dom[1] / peak["fma_tflops"], 4)
 
     plain = None
     if not args.no_plain:
@@ -343,9 +503,22 @@ def main() -> int:
                                  not args.no_accuracy)
         log(f"[bench] plain float32 kernels {plain}")
 
+    rcb = []
+    for leaf_max in args.rcb:
+        rcb.append(rcb_leg(hsr, torch, w, pos, mass, g_np, inside, leaf_max))
+        log(f"[bench] rcb fat leaves {rcb[-1]}")
+
+    unequal = None
+    if not args.no_unequal:
+        unequal = unequal_mass_leg(hsr, torch, w, pos, g_np, inside)
+        log(f"[bench] unequal masses {unequal}")
+
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w, args.cpu_seconds, g_np.astype(np.float64))
+        if args.cpu_full:
+            cpu = cpu_baseline_full(w, g_np.astype(np.float64))
+        else:
+            cpu = cpu_baseline(w, args.cpu_seconds, g_np.astype(np.float64))
         log(f"[bench] cpu baseline {cpu}")
 
     out = {
@@ -362,6 +535,7 @@ def main() -> int:
                             f"differentiable rollout of {n_c} SKS subcycles "
                             f"(autograd, position checkpoints) forward + backward")},
         "roofline": roof,
+        "peak_probe": peak,
         "counters": {"k_pair_force": measured_counters("k_pair_force", f_ms),
                      "k_pair_vjp": measured_counters("k_pair_vjp", v_ms)},
         "cpu_baseline": cpu,
@@ -380,6 +554,8 @@ def main() -> int:
             "useful_fraction": round(inside / cand, 4),
             "peak_device_memory_gb": round(torch.cuda.max_memory_allocated(dev) / 1e9, 3),
         },
+        "unequal_masses": unequal,
+        "rcb_fat_leaves": rcb,
         "accuracy": acc_info,
         "plain_fp32": plain,
         "context": "paper: 13.94 PFlops at 69.2% of peak on 1,572,864 BG/Q cores "

@@ -42,8 +42,11 @@
  *  - Return codes: HACC_SR_OK, or one of the negative codes below.
  *    Argument checks run on the host before any GPU work, so a call that
  *    fails validation touches no device memory.  n == 0 is a valid no-op.
- *    The library is not thread-safe: stream, workspace and timing state are
- *    process-wide.
+ *    The library is not thread-safe: the registered stream, workspace and
+ *    timing state are process-wide host state, read when a call is made.
+ *    Work queued on different streams may overlap on the device, so such
+ *    calls must each register their own workspace (or the caller must order
+ *    the streams): two calls in flight on one workspace race.
  */
 #ifndef HACC_SR_H
 #define HACC_SR_H
@@ -64,6 +67,11 @@ extern "C" {
 
 /* Library version, major * 10000 + minor * 100 + patch. */
 int hacc_sr_version(void);
+
+/* sha256 (64 hex digits) of the sources the library was built from: the
+ * names and bytes of its HIP sources and headers.  A binding compares it
+ * with the sources it ships with and refuses a stale library. */
+const char *hacc_sr_source_hash(void);
 
 /* Text for a return code; for HACC_SR_EHIP, the last HIP error message. */
 const char *hacc_sr_strerror(int code);
@@ -126,6 +134,54 @@ int hacc_sr_force_vjp(const double *pos, const float *mass, int64_t n,
                       const float *grad_acc, double *out_grad_pos);
 
 /*
+ * RCB fat leaves (Sec. III: the short-range solver's recursive coordinate
+ * bisection tree, nodes split at the centre of mass along the longest side
+ * of their bounding box, particles partitioned into disjoint contiguous
+ * child ranges, fat leaves sharing one interaction list).  The chaining
+ * mesh stays the coarse level: inside every cell with more than leaf_max
+ * particles the particles are reordered by the cell's RCB tree, cut until
+ * every leaf holds at most leaf_max (1 <= leaf_max <= 2^20; else
+ * HACC_SR_EINVAL).  A node whose particles all lie on one side of the
+ * centre of mass (coincident particles) is cut in two by index.  Leaves
+ * never cross cells.  The _rcb entry points need the workspace size from
+ * hacc_sr_workspace_bytes_rcb.
+ *
+ * hacc_sr_rcb_bin: the binning of hacc_sr_bin followed by the leaves.
+ * Outputs (caller-owned device arrays): cell_start, perm, sorted_rec as for
+ * hacc_sr_bin (cell_start is the same; the order inside each cell is the
+ * tree's); leaf_start (n + 1) int32: leaf l is sorted entries
+ * [leaf_start[l], leaf_start[l + 1]), for l < *n_leaves (device int32).
+ * nodes, node_split, n_nodes may all be NULL; otherwise nodes (n, 4) int32
+ * receives every internal node as (first entry, count, count of the left
+ * child, axis 0..2, or 3 for an index cut), node_split (n) float32 its
+ * split coordinate (cell-relative, as in sorted_rec), *n_nodes (device
+ * int32) their number, in no particular order.
+ */
+int hacc_sr_workspace_bytes_rcb(int64_t n, double box, float r_cut, size_t *bytes);
+int hacc_sr_rcb_bin(const double *pos, const float *mass, int64_t n, double box,
+                    float r_cut, int32_t leaf_max, int32_t *cell_start,
+                    int32_t *perm, float *sorted_rec, int32_t *leaf_start,
+                    int32_t *n_leaves, int32_t *nodes, float *node_split,
+                    int32_t *n_nodes);
+
+/*
+ * hacc_sr_force and hacc_sr_force_vjp with the RCB leaves as the work
+ * items: each leaf is one work item of at most 64 targets (larger leaves
+ * are cut into 64-target items in tree order) whose sources are the
+ * particles of the 27 cells around it within r_cut of the item's bounding
+ * box, staged once and shared by all its targets.  Same arguments, outputs
+ * and accuracy as the chaining-mesh entry points, plus leaf_max.  Each call
+ * synchronises the stream once, to read the number of leaves.
+ */
+int hacc_sr_force_rcb(const double *pos, const float *mass, int64_t n, double box,
+                      float r_cut, float eps, const float *poly, int32_t leaf_max,
+                      float *out_acc);
+int hacc_sr_force_vjp_rcb(const double *pos, const float *mass, int64_t n,
+                          double box, float r_cut, float eps, const float *poly,
+                          int32_t leaf_max, const float *grad_acc,
+                          double *out_grad_pos);
+
+/*
  * Plain versions of hacc_sr_force and hacc_sr_force_vjp at the same
  * accuracy, for comparison only: one thread per target, sources read from
  * global memory over the 27 stencil cells, the cut-off as a branch, the same
@@ -139,6 +195,45 @@ int hacc_sr_force_vjp_plain(const double *pos, const float *mass, int64_t n,
                             double box, float r_cut, float eps,
                             const float *poly, const float *grad_acc,
                             double *out_grad_pos);
+
+/*
+ * Long-range accelerations from the spectral particle-mesh solver (Sec. II):
+ * Cloud-In-Cell deposit of the masses on a periodic grid of ng^3 cells of
+ * side D = box / ng (grid point g at g D), the isotropising filter of Eq. 5
+ * exp(-k^2 (sigma D)^2 / 4) [sin(k D / 2) / (k D / 2)]^n_s (sigma in grid
+ * cells; nominal 0.8 and 3), the sixth-order periodic influence function
+ * (read as the inverse of the sixth-order central-difference Laplacian's
+ * symbol), fourth-order spectral differencing of the potential (read as the
+ * fourth-order central difference's symbol), one inverse FFT per component
+ * and CIC interpolation to the particles.  G = 1, a = -grad phi,
+ * nabla^2 phi = 4 pi rho, the mean density removed (phi(0) = 0).
+ * pos (n,3) float64, positions wrapped into [0, box); mass (n) float32;
+ * box > 0 (periodic only); ng a power of two, 8..512; out_acc (n,3)
+ * float32, input order, overwritten.  Float32 grids and FFTs; the deposit
+ * sums in fixed point, so results are bitwise reproducible.  Uses the
+ * workspace (size from hacc_sr_pm_workspace_bytes: two complex ng^3 grids).
+ */
+int hacc_sr_pm_workspace_bytes(int32_t ng, size_t *bytes);
+int hacc_sr_pm_accel(const double *pos, const float *mass, int64_t n, double box,
+                     int32_t ng, float sigma, int32_t n_s, float *out_acc);
+
+/*
+ * One full time step of the split-operator scheme (Sec. II, Eq. 6):
+ *   M_full(dt) = M_lr(dt/2) (M_sr(dt/n_c))^n_c M_lr(dt/2),
+ * in place on pos and vel ((n,3) float64; pos wrapped into [0, box)).  M_lr
+ * kicks the velocities with the long-range PM acceleration of
+ * hacc_sr_pm_accel (positions frozen); M_sr is the stream-kick-stream
+ * subcycle with the short-range force of hacc_sr_force at step dt / n_c.
+ * Newtonian coefficients (v += t a, x += t v); the cosmological factors
+ * are not printed in the paper.  box > 0 (periodic); the PM arguments as
+ * for hacc_sr_pm_accel, the short-range ones as for hacc_sr_force; n_c >= 1.
+ * acc_scratch: (n,3) float32 device array, overwritten.  Needs the larger
+ * of the two workspace sizes (hacc_sr_workspace_bytes, hacc_sr_pm_workspace_bytes).
+ */
+int hacc_sr_full_step(double *pos, double *vel, const float *mass, int64_t n,
+                      double box, int32_t ng, float sigma, int32_t n_s, float r_cut,
+                      float eps, const float *poly, double dt, int32_t n_c,
+                      float *acc_scratch);
 
 /*
  * Kick of the stream-kick-stream subcycle (Sec. II, Eq. 6):
@@ -175,13 +270,30 @@ int hacc_sr_count_pairs(const double *pos, int64_t n, double box, float r_cut,
  * Kernel timing with HIP events recorded on the library stream around each
  * launch of a pair kernel.  kernel: 0 = forward pair kernel, 1 = VJP pair
  * kernel, 2 = binning (all its kernels), 3 = work-list build, 4 = plain
- * forward kernel, 5 = plain VJP kernel.
+ * forward kernel, 5 = plain VJP kernel, 6 = RCB tree and leaf table,
+ * 7 = long-range PM solve (hacc_sr_pm_accel).
  * hacc_sr_timing_enable(1) starts recording (and clears earlier records);
  * hacc_sr_timing_read waits for the recorded events and returns the number
  * of launches and their summed duration in milliseconds.
  */
 int hacc_sr_timing_enable(int enable);
 int hacc_sr_timing_read(int kernel, int64_t *launches, double *total_ms);
+
+/*
+ * Rate probe of the float32 vector ALU, for measurement only: the peak the
+ * pair kernels are held to, at the shader clock the chip sustains under a
+ * VALU load.  kind 0: float32 fused multiply-add; 1: float32 reciprocal
+ * square root; 2: one reciprocal square root per 18 multiply-adds (the
+ * forward pair term's mix); 3: float32 multiply-add into its destination
+ * (the short v_fmac_f32 encoding).  16 independent chains per lane,
+ * waves_per_simd (1..8) one-wave workgroups per SIMD of the device, 5 timed
+ * launches.  Uses the workspace (about 2.2 MB; HACC_SR_ENOSPACE if smaller)
+ * and synchronises the stream.  out: HOST double[4]: [0] lane operations
+ * per second (an FMA counts as one operation, 2 FLOP), [1] mean shader
+ * clock during the loops in GHz, [2] shader cycles between two consecutive
+ * instructions of one wave, [3] milliseconds per launch.
+ */
+int hacc_sr_valu_probe(int kind, int waves_per_simd, double *out);
 
 #ifdef __cplusplus
 }

@@ -22,7 +22,7 @@ struct Geom {
 // Pair-kernel constants derived on the host from (r_cut, eps, poly).
 // The grid-force polynomial is evaluated in t = alpha * (s + eps) + beta,
 // which maps s in [0, r_cut^2] onto [-1, 1]; b[] are its coefficients in t
-// and db2[] those of 2 d(poly)/ds, also in t.
+// db2[] those of 2 d(poly)/ds, also in t, and dq3[] = db2[] / 3.
 struct PairParams {
     float alpha, beta;
     float eps;
@@ -31,6 +31,7 @@ struct PairParams {
                       // at least this far (squared) from the target box
     float b[6];
     float db2[5];
+    float dq3[5];
 };
 
 // One unit of pair-kernel work: T = i_count target particles of one cell,
@@ -106,6 +107,18 @@ hipError_t launch_pair_vjp(const WorkItem* items, int max_items,
                            const int* perm, Geom g, PairParams p,
                            double* out_grad, hipStream_t st);
 
+// RCB fat leaves inside the chaining cells (rcb.hip)
+hipError_t launch_rcb(const int* cell_start, int ncell, int n, int leaf_max,
+                      int* cell_list, int* counters, float4* rec, int* perm,
+                      float4* rec_tmp, int* perm_tmp, int* leafmark,
+                      int4* nodes, float* split, hipStream_t st);
+hipError_t launch_leaf_table(const int* leafmark, int* leafidx, int n, int* scan_tmp,
+                             int* leaf_start, hipStream_t st);
+hipError_t launch_leaf_items(const int* leaf_start, const int* n_leaves_dev,
+                             int max_leaves, const int* keys_sorted, int sbits,
+                             int* leaf_items, int* scan_tmp, WorkItem* items,
+                             hipStream_t st);
+
 // plain reference kernels (plain.hip)
 hipError_t launch_force_plain(const float4* rec, const int* keys_sorted,
                               const int* cell_start, const int* perm, int n,
@@ -121,6 +134,11 @@ size_t probe_clock_offset();
 int probe_ops_per_iter(int kind);
 hipError_t launch_valu_probe(int kind, int waves, int iters, void* scratch,
                              hipStream_t st);
+
+// long-range spectral PM force (pm.hip)
+size_t pm_workspace_bytes(int ng);
+hipError_t launch_pm_accel(const double* pos, const float* mass, int n, double box, int ng,
+                           float sigma, int n_s, void* ws, float* out_acc, hipStream_t st);
 
 // kick / stream (integrate.hip)
 hipError_t launch_kick(double* vel, const float* acc, int64_t m, double dt,

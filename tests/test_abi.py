@@ -109,7 +109,8 @@ def test_integrator_argument_validation(lib):
     assert lib.hacc_sr_kick_adjoint(P(16), None, 5, 0.1) == -1
     n = ctypes.c_int64()
     ms = ctypes.c_double()
-    assert lib.hacc_sr_timing_read(7, ctypes.byref(n), ctypes.byref(ms)) == -1
+    assert lib.hacc_sr_timing_read(8, ctypes.byref(n), ctypes.byref(ms)) == -1
+    assert lib.hacc_sr_timing_read(-1, ctypes.byref(n), ctypes.byref(ms)) == -1
 
 
 def test_product_path_has_no_fallback(monkeypatch, tmp_path):
@@ -133,3 +134,26 @@ def test_stale_library_is_refused(lib, monkeypatch):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(_lib.StaleLibraryError):
         _lib.load()
+
+
+def test_rcb_and_pm_argument_validation(lib):
+    poly = _poly()
+    # leaf_max outside 1..2^20
+    assert lib.hacc_sr_force_rcb(P(16), P(16), 10, 1.0, F(0.1), F(1e-5), poly, 0,
+                                 P(16)) == -1
+    assert lib.hacc_sr_force_vjp_rcb(P(16), P(16), 10, 1.0, F(0.1), F(1e-5), poly,
+                                     (1 << 20) + 1, P(16), P(16)) == -1
+    out = ctypes.c_size_t(0)
+    assert lib.hacc_sr_workspace_bytes_rcb(1000, 1.0, F(0.1), ctypes.byref(out)) == 0
+    base = ctypes.c_size_t(0)
+    assert lib.hacc_sr_workspace_bytes(1000, 1.0, F(0.1), ctypes.byref(base)) == 0
+    assert out.value > base.value
+    # PM: power-of-two grid 8..512, periodic box, sigma >= 0, 0 <= n_s <= 16
+    for ng in (4, 12, 1024):
+        assert lib.hacc_sr_pm_accel(P(16), P(16), 10, 1.0, ng, F(0.8), 3, P(16)) == -1
+    assert lib.hacc_sr_pm_accel(P(16), P(16), 10, -1.0, 64, F(0.8), 3, P(16)) == -1
+    assert lib.hacc_sr_pm_accel(P(16), P(16), 10, 1.0, 64, F(-0.1), 3, P(16)) == -1
+    assert lib.hacc_sr_pm_accel(P(16), P(16), 10, 1.0, 64, F(0.8), 17, P(16)) == -1
+    assert lib.hacc_sr_pm_accel(None, None, 0, 1.0, 64, F(0.8), 3, None) == 0
+    assert lib.hacc_sr_pm_workspace_bytes(256, ctypes.byref(out)) == 0
+    assert out.value >= 2 * 8 * 256 ** 3

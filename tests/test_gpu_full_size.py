@@ -20,16 +20,31 @@ TOL_VJP = 1e-4
 BAND = 1e-6
 
 
-def _targets(w, k_rand=1500, k_dense=500, seed=51):
+def _targets(w, k=10000, seed=51):
+    """A stratified sample of 10^4 targets: equal shares from four strata of
+    cell occupancy (quartiles of the particles' own cell counts, so the
+    sparse background and the halo cores are both represented), plus the
+    particles of the eight most populated cells and ghost-shell particles."""
     rng = np.random.default_rng(seed)
     N = hsr.grid_dim(w.box, w.r_cut)
     c = np.clip(np.floor(w.pos * (N / abs(w.box))), 0, N - 1).astype(np.int64)
     key = (c[:, 0] * N + c[:, 1]) * N + c[:, 2]
-    top = np.argsort(-np.bincount(key, minlength=N ** 3))[:8]
+    counts = np.bincount(key, minlength=N ** 3)
+    occ = counts[key]
+    n_act = w.meta["n_active"]
+    edges = np.quantile(occ[:n_act], [0.25, 0.5, 0.75])
+    stratum = np.searchsorted(edges, occ[:n_act], side="right")
+    picks = []
+    per = (k - 1000) // 4
+    for s_ in range(4):
+        members = np.flatnonzero(stratum == s_)
+        picks.append(rng.choice(members, min(per, members.size), replace=False))
+    top = np.argsort(-counts)[:8]
     dense = np.flatnonzero(np.isin(key, top))
-    dense = rng.choice(dense, min(k_dense, dense.size), replace=False)
-    pick = rng.choice(w.meta["n_active"], k_rand, replace=False)
-    return np.unique(np.concatenate([pick, dense]))
+    picks.append(rng.choice(dense, min(500, dense.size), replace=False))
+    ghosts = np.arange(n_act, w.n)
+    picks.append(rng.choice(ghosts, min(500, ghosts.size), replace=False))
+    return np.unique(np.concatenate(picks))
 
 
 def test_cfg5_full_size_sampled(cuda):

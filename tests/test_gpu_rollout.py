@@ -69,7 +69,37 @@ def test_rollout_and_gradient_vs_oracle(cuda, name):
           flush=True)
     assert np.all(dx <= 2 * 12.5 * h * h * da + 1e-15)
     assert np.all(dv <= 2 * 5 * h * da + 1e-15)
-    for got, ref in ((gx0.cpu().numpy(), gx0_ref), (gv0.cpu().numpy(), gv0_ref)):
-        rel = np.abs(got - ref).max() / np.abs(ref).max()
-        print(f"rollout gradient max rel {rel:.3e}", flush=True)
-        assert rel <= 1e-4
+    # Per particle: the reverse pass applies one VJP per subcycle, each within
+    # E_k = 1e-4 max(|V_k|, 0.1 B_k) of the float64 one (V_k the oracle VJP
+    # with that subcycle's cotangent h gv, B_k its floor).  An error in the VJP
+    # of subcycle k reaches gx0 once and gv0 with weight (k + 1/2) h (the
+    # half stream of its own subcycle and the full streams of the k earlier
+    # ones); a factor 2 covers second-order terms.  The identity part of the
+    # gradient (gx passed through) is exact in float64 and cancels.
+    bx, bv = _propagated_bounds(w, cps, h, gx)
+    for name, got, ref, bound in (("x0", gx0.cpu().numpy(), gx0_ref, bx),
+                                  ("v0", gv0.cpu().numpy(), gv0_ref, bv)):
+        dev = np.linalg.norm(got - ref, axis=1)
+        print(f"rollout gradient d{name}: max |err| / bound {np.max(dev / bound):.3e}, "
+              f"max |err| {dev.max():.3e}", flush=True)
+        assert np.all(dev <= bound)
+
+
+def _propagated_bounds(w, cps, h, gx):
+    """Per-particle bounds on the gradient errors of the rollout's reverse
+    pass, from the oracle's VJP and floor at each subcycle's cotangent."""
+    n_c = len(cps)
+    gxr = np.array(gx, dtype=np.float64, copy=True)
+    gvr = np.zeros_like(gxr)
+    bx = np.zeros(gxr.shape[0])
+    bv = np.zeros(gxr.shape[0])
+    for k in reversed(range(n_c)):
+        gvr = gvr + 0.5 * h * gxr
+        vk, bk, amb = oracle.force_vjp(cps[k], w.mass, w.box, w.r_cut, w.eps, w.poly,
+                                       h * gvr, cut_band=1e-6)
+        ek = 1e-4 * np.maximum(np.linalg.norm(vk, axis=1), 0.1 * bk) + amb
+        bx += ek
+        bv += (k + 0.5) * h * ek
+        gxr = gxr + vk
+        gvr = gvr + 0.5 * h * gxr
+    return 2.0 * bx + 1e-300, 2.0 * bv + 1e-300

@@ -38,20 +38,32 @@ def _gpu_vjp(w, g, device):
 BAND = 1e-6
 
 
-def _check(w, g, got, targets=None):
-    ref, bn, amb = oracle.force_vjp(w.pos, w.mass, w.box, w.r_cut, w.eps, w.poly,
-                                    g.astype(np.float64), targets=targets,
-                                    cut_band=BAND)
+def _check(w, g, got, targets=None, pair_floor_tol=None):
+    """Asserts the VJP error under the floor B (Newtonian and polynomial parts
+    before they cancel) and reports it under the tighter floor P (the pair
+    terms' own magnitudes (|f| + 2|f'| s)|w|); with pair_floor_tol, also
+    asserts the error under P.  Returns the max errors under B and P."""
+    ref, bn, amb, pm = oracle.force_vjp(w.pos, w.mass, w.box, w.r_cut, w.eps, w.poly,
+                                        g.astype(np.float64), targets=targets,
+                                        cut_band=BAND, pair_floor=True)
     sub = got if targets is None else got[targets]
     dev = np.linalg.norm(sub - ref, axis=1)
     lim = TOL * np.maximum(np.linalg.norm(ref, axis=1), 0.1 * bn) + amb
     clean = amb == 0.0
     err = oracle.rel_err_floored(sub[clean], ref[clean], bn[clean])
+    perr = oracle.rel_err_floored(sub[clean], ref[clean], pm[clean])
+    worst = int(np.argmax(perr)) if perr.size else 0
     print(f"{w.name}: vjp checked={sub.shape[0]} (on the cut: {(~clean).sum()}) "
-          f"max err off the cut={err.max():.3e}", flush=True)
+          f"max err off the cut={err.max():.3e}; under the pair-term floor "
+          f"max {perr.max():.3e}, {(perr > TOL).sum()} above {TOL:g} "
+          f"(worst: B/P = {bn[clean][worst] / max(pm[clean][worst], 1e-300):.1f})",
+          flush=True)
     assert np.all(np.isfinite(sub))
     assert np.all(dev <= lim)
     assert err.max() <= TOL
+    if pair_floor_tol is not None:
+        assert perr.max() <= pair_floor_tol
+    return float(err.max()), float(perr.max())
 
 
 @pytest.mark.parametrize("box", [1.0, -1.0])
@@ -83,6 +95,37 @@ def test_vjp_unequal_masses(cuda, frac):
     w.mass = m
     g = cotangent(w.n, 4)
     _check(w, g, _gpu_vjp(w, g, cuda))
+
+
+def test_vjp_coincident_unequal_masses_small_eps(cuda):
+    """Unequal masses with a small softening (1e-3 cell^2) and pairs of
+    distinct particles at exactly the same position.  A coincident pair has
+    d = 0, so its VJP term is f(0) w with f(0) = eps^(-3/2) - c_0 large; the
+    self pair must contribute exactly nothing (w = 0), which with this eps
+    would otherwise show even as a rounding residual of m_k g_k."""
+    base = _clustered(1 << 14, 32, 12, 24)
+    rng = np.random.default_rng(25)
+    dup = rng.choice(base.n, 400, replace=False)
+    pos = np.concatenate([base.pos, base.pos[dup]], axis=0)
+    w = _finish("coincident", pos, 24, 32, base.meta, eps_cells2=1e-3)
+    m = (10.0 ** rng.uniform(-1.0, 1.0, w.n) / w.n).astype(np.float32)
+    w.mass = m
+    g = cotangent(w.n, 26)
+    _check(w, g, _gpu_vjp(w, g, cuda))
+    # The forward on the same set: coincident pairs contribute d = 0.  With a
+    # softening this small the float32 frame coordinates (absolute error up
+    # to 2^-24 of two cell sides) are coarse against the softening length:
+    # a pair at s ~ eps has a relative separation error up to 2^-23 Lc /
+    # sqrt(eps), 1.2e-5 here (9.4e-7 at the workloads' 0.164 cell^2), so the
+    # bound is the larger of that and 1e-5.
+    ref, an, _ = oracle.force(w.pos, w.mass, w.box, w.r_cut, w.eps, w.poly)
+    pos_t, mass_t = to_dev(w, cuda)
+    acc = hsr.force(pos_t, mass_t, w.box, w.r_cut, w.eps, w.poly).cpu().numpy()
+    lc = abs(w.box) / hsr.grid_dim(w.box, w.r_cut)
+    bound = max(1e-5, 2.0 ** -23 * lc / np.sqrt(float(np.float32(w.eps))))
+    err = oracle.rel_err_floored(acc, ref, an).max()
+    print(f"coincident forward: max err {err:.3e} (bound {bound:.3e})", flush=True)
+    assert err <= bound
 
 
 def test_vjp_cfg4_full_and_finite_differences(cuda):
