@@ -54,3 +54,18 @@ def sks_vjp(cps, mass, box, r_cut, eps, poly, h, gx, gv, vjp_fn=None):
         gx = gx + vjp_fn(x1, h * gv)
         gv = gv + 0.5 * h * gx
     return gx, gv
+
+
+def full_step(x0, v0, mass, box, ng, r_cut, eps, poly, dt, n_c, sigma=0.8, n_s=3):
+    """One full step of the split-operator scheme (Sec. II, Eq. 6):
+    M_full(t) = M_lr(t/2) (M_sr(t/n_c))^n_c M_lr(t/2).  M_lr is a kick with
+    the long-range PM acceleration (positions frozen); M_sr is the
+    stream-kick-stream subcycle with the short-range force.  Newtonian
+    coefficients (v += t a, x += t v), float64.  Returns (x, v)."""
+    from . import pm
+    x = np.array(x0, dtype=np.float64, copy=True)
+    v = np.array(v0, dtype=np.float64, copy=True)
+    v = v + 0.5 * dt * pm.accel(x, mass, box, ng, sigma, n_s)
+    x, v, _ = sks(x, v, mass, box, r_cut, eps, poly, dt / n_c, n_c)
+    v = v + 0.5 * dt * pm.accel(x, mass, box, ng, sigma, n_s)
+    return x, v
