@@ -182,6 +182,24 @@ int hacc_sr_force_vjp_rcb(const double *pos, const float *mass, int64_t n,
                           double *out_grad_pos);
 
 /*
+ * hacc_sr_force for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid it): the
+ * same kernels and results, with no workspace.  Its scratch memory is a
+ * file-scope device array of 128 MiB in the library, which every GPU the
+ * library runs on holds until the process ends; a call whose workspace
+ * (hacc_sr_workspace_bytes for the same n, box, r_cut) exceeds 128 MiB
+ * returns HACC_SR_ENOSPACE before any GPU work (about a million particles
+ * at a few per cell).  No allocation, no event, no memset: buffers that
+ * must start at zero are cleared by kernels.  Every call on one GPU uses
+ * that GPU's one array, so calls that may overlap on one GPU (two streams,
+ * two threads) race; the caller must order them.  Runs on the registered
+ * stream; the registered workspace is neither used nor changed.
+ */
+int hacc_sr_force_noalloc(const double *pos, const float *mass, int64_t n,
+                          double box, float r_cut, float eps, const float *poly,
+                          float *out_acc);
+
+/*
  * Plain versions of hacc_sr_force and hacc_sr_force_vjp at the same
  * accuracy, for comparison only: one thread per target, sources read from
  * global memory over the 27 stencil cells, the cut-off as a branch, the same

@@ -25,7 +25,7 @@ EXPORTS = (
     "hacc_sr_timing_enable", "hacc_sr_timing_read", "hacc_sr_force_plain",
     "hacc_sr_force_vjp_plain", "hacc_sr_valu_probe", "hacc_sr_workspace_bytes_rcb",
     "hacc_sr_rcb_bin", "hacc_sr_force_rcb", "hacc_sr_force_vjp_rcb",
-    "hacc_sr_pm_workspace_bytes", "hacc_sr_pm_accel",
+    "hacc_sr_force_noalloc", "hacc_sr_pm_workspace_bytes", "hacc_sr_pm_accel",
     "hacc_sr_full_step",
 )
 
@@ -92,6 +92,7 @@ def load():
         "hacc_sr_rcb_bin": ([P, P, I64, D, F, I, P, P, P, P, P, P, P, P], I),
         "hacc_sr_force_rcb": ([P, P, I64, D, F, F, P, I, P], I),
         "hacc_sr_force_vjp_rcb": ([P, P, I64, D, F, F, P, I, P, P], I),
+        "hacc_sr_force_noalloc": ([P, P, I64, D, F, F, P, P], I),
         "hacc_sr_pm_workspace_bytes": ([I, P], I),
         "hacc_sr_pm_accel": ([P, P, I64, D, I, F, I, P], I),
         "hacc_sr_full_step": ([P, P, P, I64, D, I, F, I, F, F, P, D, I, P], I),

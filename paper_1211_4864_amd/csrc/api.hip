@@ -395,9 +395,77 @@ int force_into(const double* pos, const float* mass, int64_t n, const Geom& g,
     });
 }
 
+// ---------------------------------------------------------------- no-alloc
+
+// Scratch memory of hacc_sr_force_noalloc, for callers that cannot allocate:
+// a file-scope device array that every GPU the library runs on holds until
+// the process ends.  In host code `scratch` names a host-side stand-in, not
+// device memory, so its device address is taken once per device with
+// hipGetSymbolAddress and only that address is used.
+constexpr size_t kNoAllocBytes = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_for_current_device(void** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return HACC_SR_EDOMAIN;
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return HACC_SR_OK;
+}
+
+// Points the workspace at the scratch array for the duration of one call.
+struct WorkspaceSwap {
+    void* ws;
+    size_t bytes;
+    WorkspaceSwap(void* p, size_t b) : ws(g_ws), bytes(g_ws_bytes) {
+        g_ws = p;
+        g_ws_bytes = b;
+    }
+    ~WorkspaceSwap() {
+        g_ws = ws;
+        g_ws_bytes = bytes;
+    }
+};
+
 }  // namespace
 
 extern "C" {
+
+int hacc_sr_force_noalloc(const double* pos, const float* mass, int64_t n, double box,
+                          float r_cut, float eps, const float* poly, float* out_acc) {
+    Geom g;
+    int rc = make_geom(n, box, r_cut, &g);
+    if (rc != HACC_SR_OK) return rc;
+    PairParams P;
+    if ((rc = make_params(r_cut, eps, poly, &P)) != HACC_SR_OK) return rc;
+    if (n > 0 && (!pos || !mass || !out_acc)) return HACC_SR_EINVAL;
+    if (n == 0) return HACC_SR_OK;
+    const Layout L = layout_for(n, g);
+    if (L.total > kNoAllocBytes) return HACC_SR_ENOSPACE;
+    void* base = nullptr;
+    if ((rc = scratch_for_current_device(&base)) != HACC_SR_OK) return rc;
+    WorkspaceSwap swap(base, kNoAllocBytes);
+    // the same kernels as hacc_sr_force; every buffer that must start at
+    // zero is cleared by a fill kernel, so earlier contents do not matter
+    int* cs = ws_at<int>(L.counts);
+    float4* rec = ws_at<float4>(L.rec);
+    int* perm = nullptr;
+    if ((rc = bin_impl(pos, mass, n, g, L, cs, &perm, rec, nullptr)) != HACC_SR_OK) return rc;
+    const WorkItem* items;
+    const int* nitems;
+    if ((rc = worklist_impl(cs, g, L, &items, &nitems)) != HACC_SR_OK) return rc;
+    HIP_TRY(launch_pair_force(items, L.max_items, nitems, rec, cs, perm, g, P, out_acc,
+                              g_stream));
+    return HACC_SR_OK;
+}
+
 
 #ifndef HSR_SOURCE_SHA256
 #error "build with -DHSR_SOURCE_SHA256=<sha256 of the sources> (paper_1211_4864_amd/build.py)"
