@@ -295,6 +295,57 @@ def rcb_leg(hsr, torch, w, pos, mass, g_np, inside, leaf_max, launches=2):
             "vjp_pct_fp32_peak": round(100 * vjp / FP32_PEAK_TFLOPS, 2)}
 
 
+PM_GRID = {"cfg1": 128, "cfg2": 128, "cfg4": 128, "cfg3": 256, "cfg3s": 256, "cfg5": 512}
+
+
+def pm_leg(hsr, torch, w, pos, mass, ng, launches=3):
+    """The long-range PM solve (Sec. II) on the workload's own PM grid (the
+    grid whose 3 cells are r_cut): time per solve and its HBM rate against
+    the algorithmic bytes: per grid cell 288 B (density 8, four 3-D FFTs of
+    three passes at 16 B each, potential 16, three gradients 48, three
+    interpolation reads 24), per particle 112 B (deposit reads 28,
+    interpolation reads the position three times and writes 12)."""
+    if w.box <= 0:
+        return None
+    acc = hsr.pm_accel(pos, mass, w.box, ng)
+    torch.cuda.synchronize()
+    hsr.timing_enable(True)
+    for _ in range(launches):
+        hsr.pm_accel(pos, mass, w.box, ng, out=acc)
+    torch.cuda.synchronize()
+    n_p, ms_p = hsr.timing_read(hsr.TIMER_PM)
+    hsr.timing_enable(False)
+    ms = ms_p / max(n_p, 1)
+    algo = 288.0 * ng ** 3 + 112.0 * w.n
+    return {"ng": ng, "ms_per_solve": round(ms, 4),
+            "algorithmic_bytes": algo,
+            "roofline": {"bound": "hbm", "achieved": round(algo / (ms * 1e-3) / 1e9, 1),
+                         "peak": 8000.0, "unit": "GB/s",
+                         "frac": round(algo / (ms * 1e-3) / 8e12, 4)}}
+
+
+def full_step_leg(hsr, torch, w, pos, mass, ng, n_c=5, steps=2):
+    """One full split-operator step (Eq. 6: PM half kick, n_c short-range
+    subcycles, PM half kick) on the workload, with the grid-force polynomial
+    of the workload."""
+    if w.box <= 0:
+        return None
+    x = pos.clone()
+    v = torch.zeros_like(x)
+    acc = torch.empty((w.n, 3), dtype=torch.float32, device=pos.device)
+    dt = 1e-4
+    hsr.full_step(x, v, mass, w.box, ng, w.r_cut, w.eps, w.poly, dt, n_c, scratch=acc)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        x.copy_(pos)
+        v.zero_()
+        hsr.full_step(x, v, mass, w.box, ng, w.r_cut, w.eps, w.poly, dt, n_c, scratch=acc)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    return {"n_c": n_c, "ng": ng, "ms_per_step": round(ms, 3)}
+
+
 def plain_comparison(hsr, torch, w, pos, mass, g_np, inside, f_ms, v_ms,
                      with_accuracy, launches=2):
     """The plain float32 kernels (one thread per target, sources read from
@@ -341,6 +392,8 @@ def main() -> int:
                          "of a sample; for the small workloads cfg1, cfg2, cfg4")
     ap.add_argument("--no-unequal", action="store_true",
                     help="skip the unequal-mass leg")
+    ap.add_argument("--no-pm", action="store_true",
+                    help="skip the long-range PM and full-step legs")
     ap.add_argument("--rcb", type=int, nargs="*", default=[64],
                     help="leaf sizes of the RCB fat-leaf legs (none: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -508,6 +561,15 @@ def main() -> int:
         rcb.append(rcb_leg(hsr, torch, w, pos, mass, g_np, inside, leaf_max))
         log(f"[bench] rcb fat leaves {rcb[-1]}")
 
+    pm = None
+    full = None
+    if not args.no_pm and w.box > 0:
+        ng = PM_GRID[args.workload]
+        pm = pm_leg(hsr, torch, w, pos, mass, ng)
+        log(f"[bench] long-range PM {pm}")
+        full = full_step_leg(hsr, torch, w, pos, mass, ng)
+        log(f"[bench] full step {full}")
+
     unequal = None
     if not args.no_unequal:
         unequal = unequal_mass_leg(hsr, torch, w, pos, g_np, inside)
@@ -556,6 +618,8 @@ def main() -> int:
         },
         "unequal_masses": unequal,
         "rcb_fat_leaves": rcb,
+        "pm_long_range": pm,
+        "full_step": full,
         "accuracy": acc_info,
         "plain_fp32": plain,
         "context": "paper: 13.94 PFlops at 69.2% of peak on 1,572,864 BG/Q cores "

@@ -132,7 +132,7 @@ struct Segments {
 // size for lanes past the stencil), a register copy of the table's offsets
 // for the segment searches.  Must be called by the whole wave.
 __device__ int build_segments(const WorkItem& it, const int* __restrict__ cs,
-                              const Geom& g, Segments& sg, int* segoff) {
+                              const Geom& g, Segments& sg, int* segoff, int* mycnt) {
     const int lane = threadIdx.x;
     const int N = g.N;
     const int cz = it.key % N, cy = (it.key / N) % N, cx = it.key / (N * N);
@@ -160,11 +160,46 @@ __device__ int build_segments(const WorkItem& it, const int* __restrict__ cs,
     const int incl = wave_incl_scan(cnt);
     const int total = __shfl(incl, kWave - 1);
     *segoff = incl - cnt;
+    *mycnt = cnt;
     if (lane < kSeg) {
         sg.off[lane] = incl - cnt;
         sg.start[lane] = start;
         sg.code[lane] = code;
     }
+    if (lane == 0) sg.off[kSeg] = total;
+    return total;
+}
+
+// Gives zero length to the stencil cells that lie wholly beyond the cull
+// distance of the target box [lo, hi] and rebuilds the offsets; returns the
+// new number of sources.  A cell's box in the item frame is widened by
+// 1e-5 cell sides, far above the float32 rounding of a record's frame
+// coordinate, so every source of a dropped cell would also fail the
+// per-source cull: the kept sources and their order do not change (the
+// rounds that stage them do, and with them the grouping of the float32
+// partial sums).  Must be called by the whole wave, with each lane's count
+// from build_segments.
+__device__ int cull_segments(const WorkItem& it, Segments& sg, int cnt, float4 lo,
+                             float4 hi, float cull2, float Lc, int* segoff) {
+    const int lane = threadIdx.x;
+    const int zw = it.zlen + 2;
+    if (lane < 9 * zw && cnt > 0) {
+        const int ab = lane / zw;
+        const float a = (float)(ab / 3 - 1), b = (float)(ab % 3 - 1);
+        const float c = (float)(lane % zw - 1) - 0.5f * (float)it.zlen;
+        const float pad = 1e-5f * Lc;
+        const float xl = (a - 0.5f) * Lc - pad, xh = (a + 0.5f) * Lc + pad;
+        const float yl = (b - 0.5f) * Lc - pad, yh = (b + 0.5f) * Lc + pad;
+        const float zl = c * Lc - pad, zh = (c + 1.0f) * Lc + pad;
+        const float gx = fmaxf(fmaxf(xl - hi.x, lo.x - xh), 0.0f);
+        const float gy = fmaxf(fmaxf(yl - hi.y, lo.y - yh), 0.0f);
+        const float gz = fmaxf(fmaxf(zl - hi.z, lo.z - zh), 0.0f);
+        if (gx * gx + gy * gy + gz * gz >= cull2) cnt = 0;
+    }
+    const int incl = wave_incl_scan(cnt);
+    const int total = __shfl(incl, kWave - 1);
+    *segoff = incl - cnt;
+    if (lane < kSeg) sg.off[lane] = incl - cnt;
     if (lane == 0) sg.off[kSeg] = total;
     return total;
 }
@@ -428,8 +463,8 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_pair_force(
     const WorkItem it = items[blockIdx.x];
     const int lane = threadIdx.x;
     const float Lc = g.Lc_f;
-    int segoff;
-    const int total = build_segments(it, cs, g, sg, &segoff);
+    int segoff, mycnt;
+    build_segments(it, cs, g, sg, &segoff, &mycnt);
     const Lanes L = lane_map(it);
     // output slot, loaded now so that its latency overlaps the rounds
     const int dst = perm[L.ki >= 0 ? L.ki : it.i_begin];
@@ -438,6 +473,7 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_pair_force(
     xi = target_in_frame(xi, L.ki, it, sg, Lc);
     float4 lo, hi;
     target_box(xi, L.ki >= 0, &lo, &hi);
+    const int total = cull_segments(it, sg, mycnt, lo, hi, P.cull2, Lc, &segoff);
     const float mref = uniform(__shfl(xi.w, 0));
     const bool targets_equal = __ballot(L.ki >= 0 && xi.w != mref) == 0ull;
     const float4 pad = pad_source(lo, Lc);
@@ -494,8 +530,8 @@ __global__ __launch_bounds__(kWave) void k_pair_count(
     if ((int)blockIdx.x >= *n_items_dev) return;
     const WorkItem it = items[blockIdx.x];
     const float Lc = g.Lc_f;
-    int segoff;
-    const int total = build_segments(it, cs, g, sg, &segoff);
+    int segoff, mycnt;
+    const int total = build_segments(it, cs, g, sg, &segoff, &mycnt);
     const Lanes L = lane_map(it);
     float4 xi = L.ki >= 0 ? rec[L.ki] : make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
@@ -653,8 +689,8 @@ __global__ __launch_bounds__(kWave, kVMinWaves) void k_pair_vjp(
     const WorkItem it = items[blockIdx.x];
     const int lane = threadIdx.x;
     const float Lc = g.Lc_f;
-    int segoff;
-    const int total = build_segments(it, cs, g, sg, &segoff);
+    int segoff, mycnt;
+    build_segments(it, cs, g, sg, &segoff, &mycnt);
     const Lanes L = lane_map(it);
     // output slot, loaded now so that its latency overlaps the rounds
     const int dst = perm[L.ki >= 0 ? L.ki : it.i_begin];
@@ -664,6 +700,7 @@ __global__ __launch_bounds__(kWave, kVMinWaves) void k_pair_vjp(
     xk = target_in_frame(xk, L.ki, it, sg, Lc);
     float4 lo, hi;
     target_box(xk, L.ki >= 0, &lo, &hi);
+    const int total = cull_segments(it, sg, mycnt, lo, hi, P.cull2, Lc, &segoff);
     const float mref = uniform(__shfl(xk.w, 0));
     const bool targets_equal = __ballot(L.ki >= 0 && xk.w != mref) == 0ull;
     const float4 pad = pad_source(lo, Lc);
