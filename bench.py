@@ -55,16 +55,20 @@ KERNEL_SOURCES = ("pair.hip", "common.h", "worklist.hip")
 
 
 def kernel_source_hash() -> str:
-    """sha256 over the code of the pair kernels and of the work list that
-    orders their items (line comments and blank lines removed), to tie
-    counter readings to the code they were taken on."""
+    """sha256 over the code of the pair kernels, of the work list that orders
+    their items and of the shared definitions they use (common.h up to its
+    launch-wrapper declarations); line comments and blank lines removed.  It
+    ties counter readings to the code they were taken on."""
     import hashlib
     import re
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_1211_4864_amd", "csrc", name)) as f:
-            lines = (re.sub(r"//.*$", "", line).rstrip() for line in f.read().split("\n"))
-            h.update("\n".join(line for line in lines if line.strip()).encode())
+            text = f.read()
+        if name == "common.h":
+            text = text.split("// ---- launch wrappers", 1)[0]
+        lines = (re.sub(r"//.*$", "", line).rstrip() for line in text.split("\n"))
+        h.update("\n".join(line for line in lines if line.strip()).encode())
     return h.hexdigest()
 
 
@@ -301,10 +305,12 @@ PM_GRID = {"cfg1": 128, "cfg2": 128, "cfg4": 128, "cfg3": 256, "cfg3s": 256, "cf
 def pm_leg(hsr, torch, w, pos, mass, ng, launches=3):
     """The long-range PM solve (Sec. II) on the workload's own PM grid (the
     grid whose 3 cells are r_cut): time per solve and its HBM rate against
-    the algorithmic bytes: per grid cell 288 B (density 8, four 3-D FFTs of
-    three passes at 16 B each, potential 16, three gradients 48, three
-    interpolation reads 24), per particle 112 B (deposit reads 28,
-    interpolation reads the position three times and writes 12)."""
+    the algorithmic bytes of its passes: per grid cell 144 B (clearing the
+    fixed-point grid 8; forward z pass 16, y pass 16; the fused x pass reads
+    8 and writes two grids 16; inverse y and z passes over two grids 32
+    each; interpolation reads two grids 16), per particle 172 B (mass
+    maximum 4; cell keys 32; three radix passes 60; deposit 36;
+    interpolation 40).  Atomic traffic is not counted."""
     if w.box <= 0:
         return None
     acc = hsr.pm_accel(pos, mass, w.box, ng)
@@ -316,7 +322,7 @@ def pm_leg(hsr, torch, w, pos, mass, ng, launches=3):
     n_p, ms_p = hsr.timing_read(hsr.TIMER_PM)
     hsr.timing_enable(False)
     ms = ms_p / max(n_p, 1)
-    algo = 288.0 * ng ** 3 + 112.0 * w.n
+    algo = 144.0 * ng ** 3 + 172.0 * w.n
     return {"ng": ng, "ms_per_solve": round(ms, 4),
             "algorithmic_bytes": algo,
             "roofline": {"bound": "hbm", "achieved": round(algo / (ms * 1e-3) / 1e9, 1),

@@ -229,9 +229,11 @@ int hacc_sr_force_vjp_plain(const double *pos, const float *mass, int64_t n,
  * box > 0 (periodic only); ng a power of two, 8..512; out_acc (n,3)
  * float32, input order, overwritten.  Float32 grids and FFTs; the deposit
  * sums in fixed point, so results are bitwise reproducible.  Uses the
- * workspace (size from hacc_sr_pm_workspace_bytes: two complex ng^3 grids).
+ * workspace (size from hacc_sr_pm_workspace_bytes for the same ng and n:
+ * two complex ng^3 grids and the buffers of a sort of the n particles by
+ * grid cell); n < 2^31 - 1.
  */
-int hacc_sr_pm_workspace_bytes(int32_t ng, size_t *bytes);
+int hacc_sr_pm_workspace_bytes(int32_t ng, int64_t n, size_t *bytes);
 int hacc_sr_pm_accel(const double *pos, const float *mass, int64_t n, double box,
                      int32_t ng, float sigma, int32_t n_s, float *out_acc);
 

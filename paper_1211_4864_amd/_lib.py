@@ -93,7 +93,7 @@ def load():
         "hacc_sr_force_rcb": ([P, P, I64, D, F, F, P, I, P], I),
         "hacc_sr_force_vjp_rcb": ([P, P, I64, D, F, F, P, I, P, P], I),
         "hacc_sr_force_noalloc": ([P, P, I64, D, F, F, P, P], I),
-        "hacc_sr_pm_workspace_bytes": ([I, P], I),
+        "hacc_sr_pm_workspace_bytes": ([I, I64, P], I),
         "hacc_sr_pm_accel": ([P, P, I64, D, I, F, I, P], I),
         "hacc_sr_full_step": ([P, P, P, I64, D, I, F, I, F, F, P, D, I, P], I),
     }
@@ -320,9 +320,9 @@ def force_vjp_rcb(pos, mass, box: float, r_cut: float, eps: float, poly, grad_ac
     return out
 
 
-def pm_workspace_bytes(ng: int) -> int:
+def pm_workspace_bytes(ng: int, n: int) -> int:
     out = ctypes.c_size_t(0)
-    check(load().hacc_sr_pm_workspace_bytes(int(ng), ctypes.byref(out)))
+    check(load().hacc_sr_pm_workspace_bytes(int(ng), int(n), ctypes.byref(out)))
     return out.value
 
 
@@ -336,7 +336,7 @@ def pm_accel(pos, mass, box: float, ng: int, sigma: float = 0.8, n_s: int = 3, o
         out = torch.empty((n, 3), dtype=torch.float32, device=pos.device)
     _require(out, torch.float32, (n, 3), "out")
     with torch.cuda.device(pos.device):
-        _bind(pos.device, n, box, 0.0, need=pm_workspace_bytes(ng))
+        _bind(pos.device, n, box, 0.0, need=pm_workspace_bytes(ng, n))
         check(load().hacc_sr_pm_accel(_ptr(pos), _ptr(mass), n, float(box), int(ng),
                                       float(sigma), int(n_s), _ptr(out)))
     return out
@@ -355,7 +355,7 @@ def full_step(pos, vel, mass, box: float, ng: int, r_cut: float, eps: float, pol
         scratch = torch.empty((n, 3), dtype=torch.float32, device=pos.device)
     _require(scratch, torch.float32, (n, 3), "scratch")
     with torch.cuda.device(pos.device):
-        need = max(workspace_bytes(n, box, r_cut), pm_workspace_bytes(ng))
+        need = max(workspace_bytes(n, box, r_cut), pm_workspace_bytes(ng, n))
         _bind(pos.device, n, box, r_cut, need=need)
         check(load().hacc_sr_full_step(_ptr(pos), _ptr(vel), _ptr(mass), n, float(box),
                                        int(ng), float(sigma), int(n_s), float(r_cut),

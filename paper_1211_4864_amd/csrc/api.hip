@@ -564,7 +564,7 @@ int hacc_sr_full_step(double* pos, double* vel, const float* mass, int64_t n, do
     if (n > 0 && (!pos || !vel || !mass || !acc_scratch)) return HACC_SR_EINVAL;
     if (n == 0) return HACC_SR_OK;
     const Layout L = layout_for(n, g);
-    if (!g_ws || g_ws_bytes < std::max(L.total, pm_workspace_bytes(ng) + 256))
+    if (!g_ws || g_ws_bytes < std::max(L.total, pm_workspace_bytes(ng, n) + 256))
         return HACC_SR_ENOSPACE;
     const int64_t m = 3 * n;
     auto pm_kick = [&](double t) {
@@ -797,9 +797,10 @@ int hacc_sr_force_vjp_plain(const double* pos, const float* mass, int64_t n,
 }
 
 
-int hacc_sr_pm_workspace_bytes(int32_t ng, size_t* bytes) {
-    if (!bytes || ng < 8 || ng > 512 || (ng & (ng - 1))) return HACC_SR_EINVAL;
-    *bytes = pm_workspace_bytes(ng) + 256;
+int hacc_sr_pm_workspace_bytes(int32_t ng, int64_t n, size_t* bytes) {
+    if (!bytes || ng < 8 || ng > 512 || (ng & (ng - 1)) || n < 0) return HACC_SR_EINVAL;
+    if (n >= (int64_t)INT32_MAX) return HACC_SR_EDOMAIN;
+    *bytes = pm_workspace_bytes(ng, n) + 256;
     return HACC_SR_OK;
 }
 
@@ -811,7 +812,7 @@ int hacc_sr_pm_accel(const double* pos, const float* mass, int64_t n, double box
     if (n >= (int64_t)INT32_MAX) return HACC_SR_EDOMAIN;
     if (n > 0 && (!pos || !mass || !out_acc)) return HACC_SR_EINVAL;
     if (n == 0) return HACC_SR_OK;
-    if (!g_ws || g_ws_bytes < pm_workspace_bytes(ng) + 256) return HACC_SR_ENOSPACE;
+    if (!g_ws || g_ws_bytes < pm_workspace_bytes(ng, n) + 256) return HACC_SR_ENOSPACE;
     return timed(7, [&] {
         HIP_TRY(launch_pm_accel(pos, mass, (int)n, box, ng, sigma, n_s, ws_at<char>(0),
                                 out_acc, g_stream));

@@ -136,7 +136,7 @@ hipError_t launch_valu_probe(int kind, int waves, int iters, void* scratch,
                              hipStream_t st);
 
 // long-range spectral PM force (pm.hip)
-size_t pm_workspace_bytes(int ng);
+size_t pm_workspace_bytes(int ng, int64_t n);
 hipError_t launch_pm_accel(const double* pos, const float* mass, int n, double box, int ng,
                            float sigma, int n_s, void* ws, float* out_acc, hipStream_t st);
 

@@ -155,5 +155,10 @@ def test_rcb_and_pm_argument_validation(lib):
     assert lib.hacc_sr_pm_accel(P(16), P(16), 10, 1.0, 64, F(-0.1), 3, P(16)) == -1
     assert lib.hacc_sr_pm_accel(P(16), P(16), 10, 1.0, 64, F(0.8), 17, P(16)) == -1
     assert lib.hacc_sr_pm_accel(None, None, 0, 1.0, 64, F(0.8), 3, None) == 0
-    assert lib.hacc_sr_pm_workspace_bytes(256, ctypes.byref(out)) == 0
-    assert out.value >= 2 * 8 * 256 ** 3
+    assert lib.hacc_sr_pm_workspace_bytes(256, 1000, ctypes.byref(out)) == 0
+    assert out.value >= 2 * 8 * 256 ** 3 + 4 * 4 * 1000
+    small = out.value
+    assert lib.hacc_sr_pm_workspace_bytes(256, 10 ** 6, ctypes.byref(out)) == 0
+    assert out.value > small
+    assert lib.hacc_sr_pm_workspace_bytes(256, -1, ctypes.byref(out)) == -1
+    assert lib.hacc_sr_pm_workspace_bytes(12, 10, ctypes.byref(out)) == -1

@@ -3,7 +3,7 @@ against the float64 oracle (oracle/pm.py).  Float32 grids and FFTs spread
 their rounding over the whole field, so the bound is absolute, relative to
 the rms acceleration: max_i |a_i - a*_i| <= 1e-5 rms|a*| (a float32
 emulation of the same pipeline with library FFTs reads 4e-7; the margin
-covers the radix-2 twiddles and summation order)."""
+covers the float32 twiddles and the order of the FFT's sums)."""
 import numpy as np
 import pytest
 import torch
@@ -38,6 +38,47 @@ def test_pm_clustered_matches_oracle(cuda, ng):
     pos, _ = plummer_clustered(n, 51, 20, 0.6, 1.0 / max(ng, 32))
     mass = np.full(n, np.float32(1.0 / n))
     _check(_gpu(pos, mass, 1.0, ng, cuda), pm.accel(pos, mass, 1.0, ng), f"plummer ng={ng}")
+
+
+@pytest.mark.parametrize("ng,n", [(16, 60000), (256, 200000), (512, 100000)])
+def test_pm_grid_shapes_match_oracle(cuda, ng, n):
+    """Every transform shape of the kernels (16 = 4 x 4 with 16-line tiles,
+    256 = 16 x 16, 512 = 32 x 16 with 8-line tiles); at 512 most cells hold
+    one particle, at 16 most waves share cells."""
+    pos, _ = plummer_clustered(n, 54 + ng, 30, 0.5, 1.0 / max(ng, 32))
+    rng = np.random.default_rng(55)
+    mass = ((rng.random(n) + 0.5) / n).astype(np.float32)
+    ref = pm.accel(pos, mass.astype(np.float64), 1.0, ng)
+    _check(_gpu(pos, mass, 1.0, ng, cuda), ref, f"plummer ng={ng} n={n}")
+
+
+def test_pm_permuted_input_bitwise(cuda):
+    """The deposit sums in fixed point after a sort by cell, so the solve
+    does not depend on the input order: a permuted input gives the
+    permuted output, bitwise."""
+    n, ng = 70000, 64
+    pos, _ = plummer_clustered(n, 56, 10, 0.7, 1.0 / ng)
+    rng = np.random.default_rng(57)
+    mass = ((rng.random(n) + 0.5) / n).astype(np.float32)
+    perm = rng.permutation(n)
+    a = _gpu(pos, mass, 1.0, ng, cuda)
+    b = _gpu(pos[perm], mass[perm], 1.0, ng, cuda)
+    assert np.array_equal(a[perm], b)
+
+
+def test_pm_shared_cells(cuda):
+    """Runs of particles in one grid cell longer than a wave (and a run of
+    exactly coincident particles), beside a uniform background."""
+    rng = np.random.default_rng(58)
+    ng, D = 32, 1.0 / 32
+    lump = np.array([0.3, 0.6, 0.1]) + rng.random((5000, 3)) * 0.9 * D
+    same = np.tile([[0.71, 0.22, 0.93]], (3000, 1))
+    back = rng.random((20000, 3))
+    pos = np.concatenate([lump, same, back])
+    mass = np.concatenate([np.full(5000, 2e-5), np.full(3000, 1e-5),
+                           np.full(20000, 3e-5)]).astype(np.float32)
+    ref = pm.accel(pos, mass.astype(np.float64), 1.0, ng)
+    _check(_gpu(pos, mass, 1.0, ng, cuda), ref, "shared cells")
 
 
 def test_pm_box_units_unequal_masses_and_filter(cuda):
