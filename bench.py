@@ -124,13 +124,15 @@ def cpu_baseline_full(w, g, repeats=3):
     import oracle
     tf, tv = [], []
     pairs = 0
-    for _ in range(repeats):
+    for r in range(repeats):
         t0 = time.perf_counter()
         _, _, cnt = oracle.force(w.pos, w.mass, w.box, w.r_cut, w.eps, w.poly)
         tf.append(time.perf_counter() - t0)
+        log(f"[bench] cpu oracle forward {r + 1}/{repeats}: {tf[-1]:.2f} s")
         t0 = time.perf_counter()
         oracle.force_vjp(w.pos, w.mass, w.box, w.r_cut, w.eps, w.poly, g)
         tv.append(time.perf_counter() - t0)
+        log(f"[bench] cpu oracle VJP {r + 1}/{repeats}: {tv[-1]:.2f} s")
         pairs = int(cnt.sum())
     mf, mv = float(np.median(tf)), float(np.median(tv))
     return {"value": 2.0 * pairs / (mf + mv), "unit": "pair interactions/s",
@@ -472,14 +474,16 @@ def main() -> int:
         hsr.stream(x, v, 0.5 * h, box)
         cp.copy_(x)
         hsr.force(x, mass, box, rc, eps, poly, out=acc)
+        token = hsr.binning_token()
         hsr.kick(v, acc, h)
         hsr.stream(x, v, 0.5 * h, box)
-        # reverse subcycle at the checkpoint, loss = sum gx . x_final
+        # reverse subcycle at the checkpoint, loss = sum gx . x_final; the
+        # VJP at the checkpoint reuses the forward's binning of it
         gxx = gx.clone()
         gv.zero_()
         hsr.stream(gv, gxx, 0.5 * h, 0.0)
         hsr.kick_adjoint(gv, h, out=ga)
-        hsr.force_vjp(cp, mass, box, rc, eps, poly, ga, out=gtmp)
+        hsr.force_vjp(cp, mass, box, rc, eps, poly, ga, out=gtmp, binned=token)
         hsr.stream(gxx, gtmp, 1.0, 0.0)
         hsr.stream(gv, gxx, 0.5 * h, 0.0)
 
@@ -611,6 +615,8 @@ def main() -> int:
             "force_pair_ms": round(f_ms, 4), "vjp_pair_ms": round(v_ms, 4),
             "bin_ms": round(ms_b / max(n_b, 1), 4),
             "worklist_ms": round(ms_w / max(n_w, 1), 4),
+            "bin_and_gather_ms_per_step": round(ms_b / args.steps, 4),
+            "binnings_per_step": round(n_w / args.steps, 3),
             "fwd_interactions_per_s": inside / (f_ms * 1e-3),
             "adj_interactions_per_s": inside / (v_ms * 1e-3),
             "fwd_tflops": round(fwd_tflops, 3), "vjp_tflops": round(vjp_tflops, 3),

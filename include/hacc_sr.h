@@ -64,6 +64,7 @@ extern "C" {
                                  2 min(n, cells) + n/64 >= 2^31 work items */
 #define HACC_SR_ENOSPACE (-3) /* workspace unset or smaller than required */
 #define HACC_SR_EHIP (-4)     /* HIP runtime error; text via hacc_sr_strerror */
+#define HACC_SR_ESTALE (-5)   /* hacc_sr_force_vjp_binned: the token's binning is gone */
 
 /* Library version, major * 10000 + minor * 100 + patch. */
 int hacc_sr_version(void);
@@ -127,11 +128,33 @@ int hacc_sr_force(const double *pos, const float *mass, int64_t n, double box,
  * the derivative of the pair term of Eq. 7 (Sec. III) with respect to both
  * end points; the jump of f at r_cut is ignored.  grad_acc: (n,3) float32
  * cotangents g; out_grad_pos: (n,3) float64, input order, overwritten.
- * Re-bins from pos (nothing is kept from a forward call).
+ * Re-bins from pos.
  */
 int hacc_sr_force_vjp(const double *pos, const float *mass, int64_t n,
                       double box, float r_cut, float eps, const float *poly,
                       const float *grad_acc, double *out_grad_pos);
+
+/*
+ * Reuse of a binning for the VJP.  hacc_sr_force and hacc_sr_force_vjp
+ * leave their binning (sorted records, permutation, cell table, ordered work
+ * list) in the workspace; hacc_sr_binning_token names it (0: none).  Any
+ * other call that writes the workspace (binning, RCB, plain, PM, full step,
+ * pair count, probe), and any change of stream or workspace, retires it;
+ * kicks, streams and hacc_sr_force_noalloc do not.
+ *
+ * hacc_sr_force_vjp_binned is hacc_sr_force_vjp at the positions and
+ * masses of the call that left the binning named by `token`, without
+ * binning again: it reads them from the kept records, so later changes to
+ * the position array do not matter.  n, box and r_cut must equal that
+ * call's; eps and poly may differ.  Returns HACC_SR_ESTALE, before any GPU
+ * work, when the token is 0, retired, or names another size or geometry;
+ * the caller then uses hacc_sr_force_vjp.  In a stream-kick-stream step the
+ * reverse pass's VJP at the subcycle's force position is such a call.
+ */
+int hacc_sr_binning_token(uint64_t *token);
+int hacc_sr_force_vjp_binned(uint64_t token, int64_t n, double box, float r_cut,
+                             float eps, const float *poly, const float *grad_acc,
+                             double *out_grad_pos);
 
 /*
  * RCB fat leaves (Sec. III: the short-range solver's recursive coordinate

@@ -7,7 +7,7 @@ in ``include/hacc_sr.h``); this package only marshals arguments to it.
 from ._lib import (load, check, strerror, grid_dim, workspace_bytes, bin,
                    rcb_bin, force_rcb, force_vjp_rcb, TIMER_RCB, pm_accel,
                    pm_workspace_bytes, TIMER_PM, full_step,
-                   force, force_vjp, force_plain, force_vjp_plain, kick, stream,
+                   binning_token, force, force_vjp, force_plain, force_vjp_plain, kick, stream,
                    kick_adjoint, count_pairs, timing_enable, timing_read,
                    release_workspace, HaccSrError, EXPORTS, LIB_PATH,
                    TIMER_FORCE, TIMER_VJP, TIMER_BIN, TIMER_WORKLIST,
@@ -26,7 +26,7 @@ def __getattr__(name):
 __all__ = ["load", "check", "strerror", "grid_dim", "workspace_bytes", "bin",
            "rcb_bin", "force_rcb", "force_vjp_rcb", "TIMER_RCB", "pm_accel",
            "pm_workspace_bytes", "TIMER_PM", "full_step",
-           "force", "force_vjp", "force_plain", "force_vjp_plain", "kick", "stream", "kick_adjoint",
+           "binning_token", "force", "force_vjp", "force_plain", "force_vjp_plain", "kick", "stream", "kick_adjoint",
            "count_pairs", "timing_enable", "timing_read", "release_workspace",
            "HaccSrError", "EXPORTS", "LIB_PATH", "SRForce", "sr_force",
            "SKSRollout", "rollout_sks", "sks_forward", "valu_probe", "PROBE_FMA",

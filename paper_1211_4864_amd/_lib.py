@@ -26,10 +26,10 @@ EXPORTS = (
     "hacc_sr_force_vjp_plain", "hacc_sr_valu_probe", "hacc_sr_workspace_bytes_rcb",
     "hacc_sr_rcb_bin", "hacc_sr_force_rcb", "hacc_sr_force_vjp_rcb",
     "hacc_sr_force_noalloc", "hacc_sr_pm_workspace_bytes", "hacc_sr_pm_accel",
-    "hacc_sr_full_step",
+    "hacc_sr_full_step", "hacc_sr_binning_token", "hacc_sr_force_vjp_binned",
 )
 
-OK, EINVAL, EDOMAIN, ENOSPACE, EHIP = 0, -1, -2, -3, -4
+OK, EINVAL, EDOMAIN, ENOSPACE, EHIP, ESTALE = 0, -1, -2, -3, -4, -5
 TIMER_FORCE, TIMER_VJP, TIMER_BIN, TIMER_WORKLIST = 0, 1, 2, 3
 TIMER_FORCE_PLAIN, TIMER_VJP_PLAIN, TIMER_RCB, TIMER_PM = 4, 5, 6, 7
 
@@ -96,6 +96,8 @@ def load():
         "hacc_sr_pm_workspace_bytes": ([I, I64, P], I),
         "hacc_sr_pm_accel": ([P, P, I64, D, I, F, I, P], I),
         "hacc_sr_full_step": ([P, P, P, I64, D, I, F, I, F, F, P, D, I, P], I),
+        "hacc_sr_binning_token": ([P], I),
+        "hacc_sr_force_vjp_binned": ([ctypes.c_uint64, I64, D, F, F, P, P, P], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -226,9 +228,22 @@ def force(pos, mass, box: float, r_cut: float, eps: float, poly, out=None):
     return out
 
 
+def binning_token() -> int:
+    """Token of the binning that the last force or force_vjp call left in the
+    workspace (0: none); see force_vjp's `binned`."""
+    out = ctypes.c_uint64(0)
+    check(load().hacc_sr_binning_token(ctypes.byref(out)))
+    return out.value
+
+
 def force_vjp(pos, mass, box: float, r_cut: float, eps: float, poly, grad_acc,
-              out=None):
-    """dL/dx (n, 3) float64 for L = sum(grad_acc * acc)."""
+              out=None, binned: int | None = None):
+    """dL/dx (n, 3) float64 for L = sum(grad_acc * acc).
+
+    binned: a binning_token() taken right after the force call at these
+    positions and masses.  While that binning is still in the workspace (no
+    other binning, PM, probe or workspace change since) the VJP reuses it
+    and does not bin again; otherwise it bins from pos as usual."""
     torch = _torch()
     n = pos.shape[0]
     _require(pos, torch.float64, (n, 3), "pos")
@@ -239,6 +254,13 @@ def force_vjp(pos, mass, box: float, r_cut: float, eps: float, poly, grad_acc,
     _require(out, torch.float64, (n, 3), "out")
     with torch.cuda.device(pos.device):
         _bind(pos.device, n, box, r_cut)
+        if binned:
+            rc = load().hacc_sr_force_vjp_binned(int(binned), n, float(box), float(r_cut),
+                                                 float(eps), poly_array(poly),
+                                                 _ptr(grad_acc), _ptr(out))
+            if rc != ESTALE:
+                check(rc)
+                return out
         check(load().hacc_sr_force_vjp(_ptr(pos), _ptr(mass), n, float(box),
                                        float(r_cut), float(eps),
                                        poly_array(poly), _ptr(grad_acc),

@@ -18,6 +18,24 @@ namespace {
 hipStream_t g_stream = nullptr;
 void* g_ws = nullptr;
 size_t g_ws_bytes = 0;
+
+// The binning (sorted records, permutation, cell table and ordered work list)
+// that the last hacc_sr_force or hacc_sr_force_vjp left in the workspace,
+// named by a token for hacc_sr_force_vjp_binned.  Every other call that
+// writes the workspace, and any change of workspace or stream, retires it.
+struct KeptBinning {
+    uint64_t token;          // 0: none
+    int64_t n;
+    double box;
+    float r_cut;
+    const void* ws;
+    hipStream_t stream;
+    int* perm;
+};
+KeptBinning g_kept{};
+uint64_t g_kept_serial = 0;
+
+void retire_binning() { g_kept.token = 0; }
 char g_err[256] = "";
 
 constexpr int kTimers = 8;
@@ -378,7 +396,7 @@ int pm_check(double box, int32_t ng, float sigma, int32_t n_s) {
 // The short-range force of hacc_sr_force on a validated call: binning, work
 // list and the pair kernel, into out_acc.
 int force_into(const double* pos, const float* mass, int64_t n, const Geom& g,
-               const PairParams& P, const Layout& L, float* out_acc) {
+               const PairParams& P, const Layout& L, float* out_acc, int** perm_out = nullptr) {
     int* cs = ws_at<int>(L.counts);
     float4* rec = ws_at<float4>(L.rec);
     int* perm = nullptr;
@@ -388,11 +406,16 @@ int force_into(const double* pos, const float* mass, int64_t n, const Geom& g,
     const int* nitems;
     rc = timed(3, [&] { return worklist_impl(cs, g, L, &items, &nitems); });
     if (rc != HACC_SR_OK) return rc;
+    if (perm_out) *perm_out = perm;
     return timed(0, [&] {
         HIP_TRY(launch_pair_force(items, L.max_items, nitems, rec, cs, perm, g,
                                   P, out_acc, g_stream));
         return HACC_SR_OK;
     });
+}
+
+void keep_binning(int64_t n, double box, float r_cut, int* perm) {
+    g_kept = KeptBinning{++g_kept_serial, n, box, r_cut, g_ws, g_stream, perm};
 }
 
 // ---------------------------------------------------------------- no-alloc
@@ -471,7 +494,7 @@ int hacc_sr_force_noalloc(const double* pos, const float* mass, int64_t n, doubl
 #error "build with -DHSR_SOURCE_SHA256=<sha256 of the sources> (paper_1211_4864_amd/build.py)"
 #endif
 
-int hacc_sr_version(void) { return 200; }
+int hacc_sr_version(void) { return 201; }
 
 const char* hacc_sr_source_hash(void) { return HSR_SOURCE_SHA256; }
 
@@ -482,11 +505,13 @@ const char* hacc_sr_strerror(int code) {
         case HACC_SR_EDOMAIN: return "unsupported domain: periodic box below 3 r_cut, n >= 2^31, too many cells or work items";
         case HACC_SR_ENOSPACE: return "workspace unset or too small";
         case HACC_SR_EHIP: return g_err[0] ? g_err : "HIP runtime error";
+        case HACC_SR_ESTALE: return "the binning named by the token is no longer in the workspace";
         default: return "unknown error code";
     }
 }
 
 int hacc_sr_set_stream(void* stream) {
+    if ((hipStream_t)stream != g_stream) retire_binning();
     g_stream = (hipStream_t)stream;
     return HACC_SR_OK;
 }
@@ -511,6 +536,7 @@ int hacc_sr_workspace_bytes(int64_t n, double box, float r_cut, size_t* bytes) {
 
 int hacc_sr_set_workspace(void* dev_ptr, size_t bytes) {
     if (!dev_ptr && bytes) return HACC_SR_EINVAL;
+    if (dev_ptr != g_ws || (dev_ptr ? bytes : 0) != g_ws_bytes) retire_binning();
     g_ws = dev_ptr;
     g_ws_bytes = dev_ptr ? bytes : 0;
     return HACC_SR_OK;
@@ -519,6 +545,7 @@ int hacc_sr_set_workspace(void* dev_ptr, size_t bytes) {
 int hacc_sr_bin(const double* pos, const float* mass, int64_t n, double box,
                 float r_cut, int32_t* cell_start, int32_t* perm,
                 float* sorted_rec) {
+    retire_binning();
     Geom g;
     int rc = make_geom(n, box, r_cut, &g);
     if (rc != HACC_SR_OK) return rc;
@@ -539,6 +566,7 @@ int hacc_sr_bin(const double* pos, const float* mass, int64_t n, double box,
 
 int hacc_sr_force(const double* pos, const float* mass, int64_t n, double box,
                   float r_cut, float eps, const float* poly, float* out_acc) {
+    retire_binning();
     Geom g;
     int rc = make_geom(n, box, r_cut, &g);
     if (rc != HACC_SR_OK) return rc;
@@ -548,12 +576,16 @@ int hacc_sr_force(const double* pos, const float* mass, int64_t n, double box,
     if (n == 0) return HACC_SR_OK;
     const Layout L = layout_for(n, g);
     if ((rc = check_ws(L)) != HACC_SR_OK) return rc;
-    return force_into(pos, mass, n, g, P, L, out_acc);
+    int* perm = nullptr;
+    if ((rc = force_into(pos, mass, n, g, P, L, out_acc, &perm)) != HACC_SR_OK) return rc;
+    keep_binning(n, box, r_cut, perm);
+    return HACC_SR_OK;
 }
 
 int hacc_sr_full_step(double* pos, double* vel, const float* mass, int64_t n, double box,
                       int32_t ng, float sigma, int32_t n_s, float r_cut, float eps,
                       const float* poly, double dt, int32_t n_c, float* acc_scratch) {
+    retire_binning();
     int rc = pm_check(box, ng, sigma, n_s);
     if (rc != HACC_SR_OK) return rc;
     Geom g;
@@ -592,6 +624,7 @@ int hacc_sr_full_step(double* pos, double* vel, const float* mass, int64_t n, do
 int hacc_sr_force_vjp(const double* pos, const float* mass, int64_t n,
                       double box, float r_cut, float eps, const float* poly,
                       const float* grad_acc, double* out_grad_pos) {
+    retire_binning();
     Geom g;
     int rc = make_geom(n, box, r_cut, &g);
     if (rc != HACC_SR_OK) return rc;
@@ -617,6 +650,47 @@ int hacc_sr_force_vjp(const double* pos, const float* mass, int64_t n,
     const int* nitems;
     rc = timed(3, [&] { return worklist_impl(cs, g, L, &items, &nitems); });
     if (rc != HACC_SR_OK) return rc;
+    rc = timed(1, [&] {
+        HIP_TRY(launch_pair_vjp(items, L.max_items, nitems, rec, gs, cs, perm, g,
+                                P, out_grad_pos, g_stream));
+        return HACC_SR_OK;
+    });
+    if (rc == HACC_SR_OK) keep_binning(n, box, r_cut, perm);
+    return rc;
+}
+
+int hacc_sr_binning_token(uint64_t* token) {
+    if (!token) return HACC_SR_EINVAL;
+    *token = g_kept.token;
+    return HACC_SR_OK;
+}
+
+int hacc_sr_force_vjp_binned(uint64_t token, int64_t n, double box, float r_cut, float eps,
+                             const float* poly, const float* grad_acc,
+                             double* out_grad_pos) {
+    Geom g;
+    int rc = make_geom(n, box, r_cut, &g);
+    if (rc != HACC_SR_OK) return rc;
+    PairParams P;
+    if ((rc = make_params(r_cut, eps, poly, &P)) != HACC_SR_OK) return rc;
+    if (n > 0 && (!grad_acc || !out_grad_pos)) return HACC_SR_EINVAL;
+    if (n == 0) return HACC_SR_OK;
+    if (token == 0 || token != g_kept.token || n != g_kept.n || box != g_kept.box ||
+        r_cut != g_kept.r_cut || g_ws != g_kept.ws || g_stream != g_kept.stream)
+        return HACC_SR_ESTALE;
+    const Layout L = layout_for(n, g);
+    if ((rc = check_ws(L)) != HACC_SR_OK) return rc;
+    int* cs = ws_at<int>(L.counts);
+    float4* rec = ws_at<float4>(L.rec);
+    float4* gs = ws_at<float4>(L.gsorted);
+    int* perm = g_kept.perm;
+    const WorkItem* items = ws_at<WorkItem>(L.items_sorted);
+    const int* nitems = ws_at<int>(L.cell_items) + L.ncell;
+    rc = timed(2, [&] {
+        HIP_TRY(launch_gather_vec3(grad_acc, perm, (int)n, gs, g_stream));
+        return HACC_SR_OK;
+    });
+    if (rc != HACC_SR_OK) return rc;
     return timed(1, [&] {
         HIP_TRY(launch_pair_vjp(items, L.max_items, nitems, rec, gs, cs, perm, g,
                                 P, out_grad_pos, g_stream));
@@ -638,6 +712,7 @@ int hacc_sr_rcb_bin(const double* pos, const float* mass, int64_t n, double box,
                     float r_cut, int32_t leaf_max, int32_t* cell_start, int32_t* perm,
                     float* sorted_rec, int32_t* leaf_start, int32_t* n_leaves,
                     int32_t* nodes, float* node_split, int32_t* n_nodes) {
+    retire_binning();
     Geom g;
     int rc = make_geom(n, box, r_cut, &g);
     if (rc != HACC_SR_OK) return rc;
@@ -690,6 +765,7 @@ int hacc_sr_rcb_bin(const double* pos, const float* mass, int64_t n, double box,
 int hacc_sr_force_rcb(const double* pos, const float* mass, int64_t n, double box,
                       float r_cut, float eps, const float* poly, int32_t leaf_max,
                       float* out_acc) {
+    retire_binning();
     Geom g;
     int rc = make_geom(n, box, r_cut, &g);
     if (rc != HACC_SR_OK) return rc;
@@ -717,6 +793,7 @@ int hacc_sr_force_rcb(const double* pos, const float* mass, int64_t n, double bo
 int hacc_sr_force_vjp_rcb(const double* pos, const float* mass, int64_t n, double box,
                           float r_cut, float eps, const float* poly, int32_t leaf_max,
                           const float* grad_acc, double* out_grad_pos) {
+    retire_binning();
     Geom g;
     int rc = make_geom(n, box, r_cut, &g);
     if (rc != HACC_SR_OK) return rc;
@@ -745,6 +822,7 @@ int hacc_sr_force_vjp_rcb(const double* pos, const float* mass, int64_t n, doubl
 int hacc_sr_force_plain(const double* pos, const float* mass, int64_t n,
                         double box, float r_cut, float eps, const float* poly,
                         float* out_acc) {
+    retire_binning();
     Geom g;
     int rc = make_geom(n, box, r_cut, &g);
     if (rc != HACC_SR_OK) return rc;
@@ -771,6 +849,7 @@ int hacc_sr_force_vjp_plain(const double* pos, const float* mass, int64_t n,
                             double box, float r_cut, float eps,
                             const float* poly, const float* grad_acc,
                             double* out_grad_pos) {
+    retire_binning();
     Geom g;
     int rc = make_geom(n, box, r_cut, &g);
     if (rc != HACC_SR_OK) return rc;
@@ -806,6 +885,7 @@ int hacc_sr_pm_workspace_bytes(int32_t ng, int64_t n, size_t* bytes) {
 
 int hacc_sr_pm_accel(const double* pos, const float* mass, int64_t n, double box,
                      int32_t ng, float sigma, int32_t n_s, float* out_acc) {
+    retire_binning();
     int rc = pm_check(box, ng, sigma, n_s);
     if (rc != HACC_SR_OK) return rc;
     if (n < 0) return HACC_SR_EINVAL;
@@ -845,6 +925,7 @@ int hacc_sr_kick_adjoint(const double* grad_vel, float* grad_acc, int64_t n,
 
 int hacc_sr_count_pairs(const double* pos, int64_t n, double box, float r_cut,
                         float eps, int64_t* out_counts) {
+    retire_binning();
     Geom g;
     int rc = make_geom(n, box, r_cut, &g);
     if (rc != HACC_SR_OK) return rc;
@@ -872,6 +953,7 @@ int hacc_sr_count_pairs(const double* pos, int64_t n, double box, float r_cut,
 }
 
 int hacc_sr_valu_probe(int kind, int waves_per_simd, double* out) {
+    retire_binning();
     if (kind < 0 || kind > 3 || waves_per_simd < 1 || waves_per_simd > 8 || !out)
         return HACC_SR_EINVAL;
     const size_t need = probe_scratch_bytes();

@@ -162,3 +162,23 @@ def test_rcb_and_pm_argument_validation(lib):
     assert out.value > small
     assert lib.hacc_sr_pm_workspace_bytes(256, -1, ctypes.byref(out)) == -1
     assert lib.hacc_sr_pm_workspace_bytes(12, 10, ctypes.byref(out)) == -1
+
+
+def test_binned_vjp_refuses_without_token(lib):
+    """No GPU work: a token of 0 (or one never issued) is refused before any
+    launch, and the token query validates its pointer."""
+    P, F = ctypes.c_void_p, ctypes.c_float
+    poly = (ctypes.c_float * 6)(*([0.0] * 6))
+    tok = ctypes.c_uint64(7)
+    assert lib.hacc_sr_binning_token(None) == -1
+    assert lib.hacc_sr_binning_token(ctypes.byref(tok)) == 0
+    assert tok.value == 0
+    for t in (0, 12345):
+        assert lib.hacc_sr_force_vjp_binned(ctypes.c_uint64(t), 100, 1.0, F(0.05), F(1e-4),
+                                            poly, P(16), P(16)) == -5
+    # argument checks come first; n = 0 is a no-op
+    assert lib.hacc_sr_force_vjp_binned(ctypes.c_uint64(0), 100, 1.0, F(-0.05), F(1e-4),
+                                        poly, P(16), P(16)) == -1
+    assert lib.hacc_sr_force_vjp_binned(ctypes.c_uint64(0), 0, 1.0, F(0.05), F(1e-4),
+                                        poly, None, None) == 0
+    assert "token" in _lib.strerror(-5)
